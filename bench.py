@@ -1,0 +1,198 @@
+"""Benchmark: SU(3) heat-bath + overrelaxation link updates per second on
+32^4 lattices, FP32 batched against FP64 single-lattice, on one MI355X.
+
+A step is one sweep (1 Cabibbo-Marinari heat-bath pass with
+Kennedy-Pendleton draws + 4 overrelaxation passes, even/odd checkerboard per
+direction, plus the fp64 plaquette of the sweep) over every lattice of the
+workload.  One link update = one link through one pass, so a 32^4 sweep is
+5 * 4 * 32^4 = 20,971,520 link updates.  Inputs are synthetic hot starts
+(Haar links from Philox) at beta = 6.0, resident in HBM before timing.
+
+Printed: one JSON line (rank 0) with the headline value (FP32-R12 batched
+link updates/s), the FP64 single-lattice figure, the roofline of the
+dominant kernel (the overrelaxation phase) from HIP events recorded around
+every phase launch, and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+LINK_BYTES = {"fp64": 144, "fp32": 72, "fp32_r12": 48}
+PHASE_RECORDS = 9  # 8 link records read + 1 written per updated link (4V reads + V/2 writes per phase)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_variant(m, torch, prec, n_lat, dims, steps, warmup, beta=6.0, n_or=4):
+    """Time `steps` sweeps of n_lat lattices (batched graph path), then
+    `steps` more with per-phase HIP events to get kernel durations."""
+    fields = [m.Field(dims, prec) for _ in range(n_lat)]
+    for i, f in enumerate(fields):
+        m.su3_init_hot(f, 3, i)
+    params = m.hb_params(n_or=n_or, n_hb_hits=1, hb_max_tries=64, reunit_every=10 if prec != "fp64" else 0)
+    betas = [beta] * n_lat
+    seeds = [3] * n_lat
+    lids = list(range(n_lat))
+    sweep = 0
+    for _ in range(warmup):
+        m.su3_batch_sweep_hb_or(fields, betas, seeds, lids, sweep, 1, params)
+        sweep += 1
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    plaq = None
+    for _ in range(steps):
+        plaq = m.su3_batch_sweep_hb_or(fields, betas, seeds, lids, sweep, 1, params)
+        sweep += 1
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    # kernel durations: same kernels launched eagerly with events around each phase
+    m.su3_profile_enable(True)
+    for _ in range(steps):
+        m.su3_batch_sweep_hb_or(fields, betas, seeds, lids, sweep, 1, params)
+        sweep += 1
+    torch.cuda.synchronize()
+    hb_ms, hb_n = m.su3_profile_read(0)
+    or_ms, or_n = m.su3_profile_read(1)
+    m.su3_profile_enable(False)
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    updates = 5 * 4 * V * n_lat * steps if n_or == 4 else (1 + n_or) * 4 * V * n_lat * steps
+    out = {
+        "prec": prec, "n_lat": n_lat, "wall_s": wall, "event_ms": ev_ms,
+        "ms_per_step": wall * 1e3 / steps, "updates_per_s": updates / wall,
+        "hb_kernel_us": 1e3 * hb_ms / max(hb_n, 1), "or_kernel_us": 1e3 * or_ms / max(or_n, 1),
+        "hb_launches": hb_n, "or_launches": or_n, "plaq_last": float(plaq[-1].mean()),
+        "phase_links": V // 2 * n_lat,
+    }
+    for f in fields:
+        f.close()
+    return out
+
+
+def roofline(v):
+    per_launch = v["phase_links"] * PHASE_RECORDS * LINK_BYTES[v["prec"]]
+    achieved = per_launch / (v["or_kernel_us"] * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"k_phase<{v['prec']}, OR>", "algorithmic_bytes_per_launch": per_launch,
+            "avg_launch_us": round(v["or_kernel_us"], 2)}
+
+
+def cpu_baseline(dims, threads):
+    """The FP64 oracle (as it stands) on one 32^4 sweep (1 HB + 4 OR) from a
+    hot start; the hot start is not timed."""
+    import oracle
+    oracle.set_threads(threads)
+    U = oracle.init_hot(dims, 3, 0)
+    t0 = time.perf_counter()
+    oracle.sweep_hb_or(dims, U, 6.0, 3, 0, 0, 1, n_or=4)
+    dt = time.perf_counter() - t0
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    return {"value": round(5 * 4 * V / dt, 1), "unit": "link updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 sweep (1 HB + 4 OR) of one {dims[0]}^4 FP64 lattice from a hot start, "
+                      f"{threads} OpenMP threads, {dt:.1f} s"}
+
+
+def copy_calibration(torch, gib=1.0):
+    """A plain device-to-device copy of known size (for scaling HBM counters)."""
+    n = int(gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--lattice", type=int, default=32)
+    ap.add_argument("--batch", type=int, default=4, help="lattices in the FP32 batched run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="", help="comma list of variants to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch)")
+    ap.add_argument("--copy-calibration", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(independent lattices would shard across GPUs with no communication).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    import paper_1510_04675_amd as m
+    m.lib()
+    if a.copy_calibration:
+        copy_calibration(torch)
+        return
+    L = a.lattice
+    dims = [L, L, L, L]
+    want = set(a.only.split(",")) if a.only else {"fp64", "fp32", "fp32_r12", "fp32_batch", "r12_batch"}
+    res = {}
+    plan = [("fp64", "fp64", 1), ("fp32", "fp32", 1), ("fp32_r12", "fp32_r12", 1),
+            ("fp32_batch", "fp32", a.batch), ("r12_batch", "fp32_r12", a.batch)]
+    for name, prec, n in plan:
+        if name not in want:
+            continue
+        log(f"bench: {name} ({n} x {L}^4) ...")
+        res[name] = run_variant(m, torch, prec, n, dims, a.steps, a.warmup)
+        log(f"bench: {name}: {res[name]['updates_per_s']:.3e} link updates/s, "
+            f"OR kernel {res[name]['or_kernel_us']:.1f} us, HB kernel {res[name]['hb_kernel_us']:.1f} us")
+    head = res.get("r12_batch") or next(iter(res.values()))
+    cpu = None
+    if not a.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"bench: cpu baseline (oracle, {threads} threads) ...")
+        cpu = cpu_baseline(dims, threads)
+        log(f"bench: cpu baseline {cpu['value']:.3e} link updates/s")
+    line = {
+        "metric": "SU(3) link updates/s (HB+OR, 32^4) FP32-batched vs FP64; % HBM roofline",
+        "value": round(head["updates_per_s"], 1),
+        "unit": "link updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head["prec"] != "fp64" else "f64",
+        "data": "synthetic (Haar hot start from Philox seed 3, beta 6.0)",
+        "config": {"workload": f"HB+OR sweeps (1 HB + 4 OR), {head['n_lat']} x {L}^4, {head['prec']} links",
+                   "lattice": f"{L}^4", "n_lattices": head["n_lat"], "storage": head["prec"], "beta": 6.0,
+                   "n_or": 4, "sampler": "Kennedy-Pendleton", "parallelism": "single GPU"},
+        "roofline": roofline(head),
+        "cpu_baseline": cpu,
+        "variants": {k: {"link_updates_per_s": round(v["updates_per_s"], 1), "ms_per_step": round(v["ms_per_step"], 4),
+                         "or_kernel_us": round(v["or_kernel_us"], 2), "hb_kernel_us": round(v["hb_kernel_us"], 2),
+                         "or_hbm_frac": roofline(v)["frac"], "plaq_after": round(v["plaq_last"], 8)}
+                     for k, v in res.items()},
+    }
+    if "fp64" in res:
+        line["fp64_single_link_updates_per_s"] = round(res["fp64"]["updates_per_s"], 1)
+        line["speedup_fp32_batched_vs_fp64"] = round(head["updates_per_s"] / res["fp64"]["updates_per_s"], 3)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

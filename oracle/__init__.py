@@ -28,7 +28,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no intrinsics)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-std=c99", "-O2", "-fopenmp", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -47,6 +47,9 @@ def lib():
         sig = {
             "orc_philox": (None, [P, P, P]),
             "orc_u01": (d, [u32]),
+            "orc_ln": (d, [d]),
+            "orc_exp": (d, [d]),
+            "orc_cossin_2pi": (None, [d, P, P]),
             "orc_init_cold": (None, [P, P]),
             "orc_init_hot": (None, [P, P, u32, u32]),
             "orc_reunitarize": (None, [P, P]),
@@ -130,6 +133,23 @@ def philox(ctr, key) -> np.ndarray:
 
 def u01(x: int) -> float:
     return lib().orc_u01(int(x) & 0xFFFFFFFF)
+
+
+def det_ln(x: float) -> float:
+    """The oracle's fixed-sequence natural logarithm."""
+    return lib().orc_ln(float(x))
+
+
+def det_exp(x: float) -> float:
+    """The oracle's fixed-sequence exponential."""
+    return lib().orc_exp(float(x))
+
+
+def det_cossin_2pi(u: float):
+    """The oracle's fixed-sequence (cos 2 pi u, sin 2 pi u)."""
+    c, s = C.c_double(), C.c_double()
+    lib().orc_cossin_2pi(float(u), C.byref(c), C.byref(s))
+    return c.value, s.value
 
 
 def init_cold(dims) -> np.ndarray:

@@ -63,6 +63,76 @@ void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
 /* Uniform in (0,1) from the top 23 bits: (2*(x>>9)+1) * 2^-24. */
 double orc_u01(uint32_t x) { return ((double)(x >> 9) * 2.0 + 1.0) * 0x1p-24; }
 
+/* ------------------------------------------------------------------ */
+/* Elementary functions of the random draws.  Each is a fixed sequence  */
+/* of IEEE-754 double operations (no fused multiply-add), so that any   */
+/* implementation taking the same steps produces the same bits:         */
+/*  ln x:   x = m 2^e with m in [sqrt(1/2), sqrt(2)), s = (m-1)/(m+1),   */
+/*          ln m = 2 s (1 + s^2/3 + ... + s^22/23) summed by Horner in   */
+/*          s^2, ln x = e ln2_hi + (e ln2_lo + ln m).                    */
+/*  cos, sin of 2 pi u (u in [0,1]): q = nearest integer to 4u,          */
+/*          v = u - q/4, t = 2 pi v in [-pi/4, pi/4], Taylor series of   */
+/*          cos t to t^18 and sin t to t^19 by Horner in t^2, then q     */
+/*          quarter turns.                                               */
+/*  exp y:  n = nearest integer to y/ln2, r = (y - n ln2_hi) - n ln2_lo, */
+/*          Taylor series to r^17 by Horner, times 2^n.                  */
+/* ------------------------------------------------------------------ */
+/* ln 2 split so that n * LN2_HI is exact for |n| < 2^11 (Cody-Waite). */
+static const double LN2_HI = 0x1.62e42feep-1;
+static const double LN2_LO = 0x1.a39ef35793c76p-33;
+static const double INV_LN2 = 1.44269504088896340736;
+static const double TWO_PI = 6.28318530717958647693;
+static const double SQRT_HALF = 0.70710678118654752440;
+static const double FACT[21] = { 1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0, 40320.0, 362880.0, 3628800.0,
+                                 39916800.0, 479001600.0, 6227020800.0, 87178291200.0, 1307674368000.0,
+                                 20922789888000.0, 355687428096000.0, 6402373705728000.0,
+                                 121645100408832000.0, 2432902008176640000.0 };
+
+double orc_ln(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < SQRT_HALF) {
+        m = 2.0 * m;
+        e -= 1;
+    }
+    double s = (m - 1.0) / (m + 1.0);
+    double z = s * s;
+    double p = 1.0 / 23.0;
+    for (int k = 10; k >= 0; k--) p = p * z + 1.0 / (double)(2 * k + 1);
+    double de = (double)e;
+    return de * LN2_HI + (de * LN2_LO + 2.0 * s * p);
+}
+
+void orc_cossin_2pi(double u, double* c, double* s)
+{
+    double q = floor(4.0 * u + 0.5);
+    double v = u - 0.25 * q;
+    double t = TWO_PI * v;
+    double t2 = t * t;
+    double ps = -1.0 / FACT[19];
+    for (int k = 8; k >= 0; k--) ps = ps * t2 + ((k & 1) ? -1.0 : 1.0) / FACT[2 * k + 1];
+    double pc = -1.0 / FACT[18];
+    for (int k = 8; k >= 0; k--) pc = pc * t2 + ((k & 1) ? -1.0 : 1.0) / FACT[2 * k];
+    double s0 = t * ps, c0 = pc;
+    switch (((int)q) & 3) {
+    case 0: *c = c0; *s = s0; break;
+    case 1: *c = -s0; *s = c0; break;
+    case 2: *c = -c0; *s = -s0; break;
+    default: *c = s0; *s = -c0; break;
+    }
+}
+
+double orc_exp(double y)
+{
+    if (y < -745.0) return 0.0;
+    double n = floor(y * INV_LN2 + 0.5);
+    double r = (y - n * LN2_HI) - n * LN2_LO;
+    double p = 1.0 / FACT[17];
+    for (int k = 16; k >= 0; k--) p = p * r + 1.0 / FACT[k];
+    return ldexp(p, (int)n);
+}
+
 static uint32_t word1(int purpose, int mu, int sub, int hit, int draw)
 {
     return ((uint32_t)purpose << 28) | ((uint32_t)mu << 24) | ((uint32_t)sub << 20) |
@@ -85,10 +155,11 @@ static void normals4(uint32_t seed, uint32_t lid, uint32_t c0, uint32_t c1, uint
     double u[4];
     uniforms4(seed, lid, c0, c1, c23, u);
     for (int h = 0; h < 2; h++) {
-        double r = sqrt(-2.0 * log(u[2 * h]));
-        double ph = 2.0 * PI * u[2 * h + 1];
-        z[2 * h] = r * cos(ph);
-        z[2 * h + 1] = r * sin(ph);
+        double r = sqrt(-2.0 * orc_ln(u[2 * h]));
+        double c, s;
+        orc_cossin_2pi(u[2 * h + 1], &c, &s);
+        z[2 * h] = r * c;
+        z[2 * h + 1] = r * s;
     }
 }
 
@@ -423,12 +494,13 @@ static int sample_g0(double alpha, int sampler, int max_tries, uint32_t seed, ui
         double u[4];
         uniforms4(seed, lid, c0, word1(P_HB, mu, sub, hit, t), sweep, u);
         if (sampler == SAMPLER_KP) {
-            double c = cos(2.0 * PI * u[1]);
-            double delta = -(log(u[0]) + c * c * log(u[2])) / alpha;
+            double c, sn;
+            orc_cossin_2pi(u[1], &c, &sn);
+            double delta = -(orc_ln(u[0]) + c * c * orc_ln(u[2])) / alpha;
             if (u[3] * u[3] <= 1.0 - 0.5 * delta) { *g0 = 1.0 - delta; return 1; }
         } else {
-            double e = exp(-2.0 * alpha);
-            double x = 1.0 + log(e + u[0] * (1.0 - e)) / alpha;
+            double e = orc_exp(-2.0 * alpha);
+            double x = 1.0 + orc_ln(e + u[0] * (1.0 - e)) / alpha;
             if (u[1] * u[1] <= 1.0 - x * x) { *g0 = x; return 1; }
         }
     }
@@ -510,9 +582,10 @@ static int update_link(const geom* g, double* U, int64_t i, int mu, int kind, do
                 uniforms4(seed, lid, (uint32_t)i, word1(P_HB_DIR, mu, s, h, 0), sweep, u);
                 double ct = 2.0 * u[0] - 1.0;
                 double stt = sqrt(fmax(0.0, 1.0 - ct * ct));
-                double phi = 2.0 * PI * u[1];
+                double cp, sp;
+                orc_cossin_2pi(u[1], &cp, &sp);
                 double sr = sqrt(fmax(0.0, 1.0 - g0 * g0));
-                double g1 = sr * stt * cos(phi), g2 = sr * stt * sin(phi), g3 = sr * ct;
+                double g1 = sr * stt * cp, g2 = sr * stt * sp, g3 = sr * ct;
                 cx gm[2][2] = { { g0 + I * g3, g2 + I * g1 }, { -g2 + I * g1, g0 - I * g3 } };
                 for (int p = 0; p < 2; p++)
                     for (int q = 0; q < 2; q++) r[p][q] = gm[p][0] * vd[0][q] + gm[p][1] * vd[1][q];

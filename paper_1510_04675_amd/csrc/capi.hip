@@ -1,0 +1,1262 @@
+// capi.hip -- host side of the C ABI declared in include/msmc.h: argument
+// validation, field memory, descriptor tables, the sweep / HMC / flow /
+// prolongation drivers, HIP graph capture of batched sweeps, the launch-shape
+// autotuner and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/msmc.h"
+#include "kernels.hpp"
+
+using namespace msmc;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int32_t fail(int32_t code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(SU3_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Small device helpers: tables are written by kernels whose arguments carry
+// the values, so updates are ordered on the stream and can be captured.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kDescChunk = 20;
+struct DescPack {
+    LatDesc d[kDescChunk];
+    int n, off;
+};
+constexpr int kIntChunk = 480;
+struct IntPack {
+    int v[kIntChunk];
+    int n, off;
+};
+}  // namespace
+
+__global__ void k_fill_descs(DescPack p, LatDesc* out)
+{
+    const int i = threadIdx.x;
+    if (i < p.n) out[p.off + i] = p.d[i];
+}
+
+__global__ void k_fill_ints(IntPack p, int* out)
+{
+    for (int i = threadIdx.x; i < p.n; i += blockDim.x) out[p.off + i] = p.v[i];
+}
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v)
+{
+    if (threadIdx.x == 0) *p = v;
+}
+
+static hipError_t upload_descs(LatDesc* dst, const std::vector<LatDesc>& src, hipStream_t st)
+{
+    for (size_t o = 0; o < src.size(); o += kDescChunk) {
+        DescPack p;
+        memset(&p, 0, sizeof p);
+        p.n = (int)std::min<size_t>(kDescChunk, src.size() - o);
+        p.off = (int)o;
+        for (int i = 0; i < p.n; i++) p.d[i] = src[o + i];
+        k_fill_descs<<<1, 64, 0, st>>>(p, dst);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static hipError_t upload_ints(int* dst, const std::vector<int>& src, hipStream_t st)
+{
+    for (size_t o = 0; o < src.size(); o += kIntChunk) {
+        IntPack p;
+        memset(&p, 0, sizeof p);
+        p.n = (int)std::min<size_t>(kIntChunk, src.size() - o);
+        p.off = (int)o;
+        for (int i = 0; i < p.n; i++) p.v[i] = src[o + i];
+        k_fill_ints<<<1, 256, 0, st>>>(p, dst);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Fields
+// ---------------------------------------------------------------------------
+static size_t padded_stride(size_t n, size_t elem)
+{
+    size_t lines = (n * elem + 127) / 128;
+    if (lines == 0) lines = 1;
+    if ((lines & 1) == 0) lines += 1;
+    return lines * 128 / elem;
+}
+
+struct su3_field_s;
+
+// Device tables for a set of lattices of one precision.
+struct Plan {
+    int nlat = 0;
+    int prec = 0;
+    int phase_block = 256, remap = 1;
+    LatDesc* d_descs = nullptr;  // nlat entries
+    int* d_bbeg_phase = nullptr;
+    int* d_bbeg_link = nullptr;
+    int* d_bbeg_site = nullptr;
+    int nblk_phase = 0, nblk_link = 0, nblk_site = 0;
+    double* d_partials = nullptr;
+    double* d_out = nullptr;  // reduction results
+    int out_cap = 0;
+    uint64_t* d_sweep = nullptr;
+    unsigned long long* d_exh = nullptr;
+    std::vector<LatDesc> host_descs;
+    std::vector<int> bbeg_phase_h, bbeg_link_h, bbeg_site_h;
+
+    void release()
+    {
+        hipFree(d_descs);
+        hipFree(d_bbeg_phase);
+        hipFree(d_bbeg_link);
+        hipFree(d_bbeg_site);
+        hipFree(d_partials);
+        hipFree(d_out);
+        hipFree(d_sweep);
+        hipFree(d_exh);
+        d_descs = nullptr;
+        d_bbeg_phase = d_bbeg_link = d_bbeg_site = nullptr;
+        d_partials = d_out = nullptr;
+        d_sweep = nullptr;
+        d_exh = nullptr;
+        out_cap = 0;
+    }
+    Grid grid_phase() const { return Grid{ d_descs, d_bbeg_phase, nlat, nblk_phase, phase_block, remap }; }
+    Grid grid_link(const LatDesc* descs = nullptr) const
+    {
+        return Grid{ descs ? descs : d_descs, d_bbeg_link, nlat, nblk_link, 256, 1 };
+    }
+    Grid grid_site(const LatDesc* descs = nullptr) const
+    {
+        return Grid{ descs ? descs : d_descs, d_bbeg_site, nlat, nblk_site, 256, 0 };
+    }
+};
+
+struct su3_field_s {
+    int L[4];
+    int V = 0, Vh = 0;
+    int prec = 0, NC = 18;
+    size_t cs = 0, cs8 = 0, bytes = 0, bytes8 = 0;
+    void* data = nullptr;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    // scratch
+    void* alt[2] = { nullptr, nullptr };
+    void* aux8 = nullptr;
+    LatDesc* d_extra = nullptr;  // 8 descriptor variants (HMC / flow ping-pong)
+    Plan plan;                    // single-lattice tables
+    bool plan_ready = false;
+    int64_t last_exhausted = 0;
+    Geo geo() const
+    {
+        Geo g;
+        for (int m = 0; m < 4; m++) g.L[m] = L[m];
+        g.h0 = L[0] / 2;
+        g.Vh = Vh;
+        return g;
+    }
+};
+
+static int32_t check_dims(const int32_t* dims)
+{
+    if (!dims) return fail(SU3_ERR_ARG, "dims is NULL");
+    long long V = 1;
+    for (int m = 0; m < 4; m++) {
+        if (dims[m] < 2 || (dims[m] & 1))
+            return fail(SU3_ERR_SHAPE, "every extent must be even and >= 2 (dims[" + std::to_string(m) +
+                                           "] = " + std::to_string(dims[m]) + ")");
+        V *= dims[m];
+        if (V > (1LL << 28)) return fail(SU3_ERR_SHAPE, "volume exceeds 2^28 sites");
+    }
+    return SU3_OK;
+}
+
+static void layout(const int32_t* dims, int prec, size_t& cs, size_t& cs8, size_t& bytes, size_t& bytes8)
+{
+    long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+    const size_t Vh = (size_t)(V / 2);
+    const size_t rb = prec_real_bytes(prec);
+    cs = padded_stride(Vh, rb);
+    cs8 = padded_stride(Vh, rb);
+    bytes = 8 * (size_t)prec_ncomp(prec) * cs * rb;
+    bytes8 = 8 * 8 * cs8 * rb;
+}
+
+static int32_t check_field(su3_field f)
+{
+    if (!f) return fail(SU3_ERR_ARG, "field handle is NULL");
+    return SU3_OK;
+}
+
+static LatDesc base_desc(const su3_field_s* f)
+{
+    LatDesc d;
+    memset(&d, 0, sizeof d);
+    d.U = f->data;
+    d.aux = f->aux8;
+    d.aux2 = f->alt[0];
+    d.cs = f->cs;
+    d.cs8 = f->cs8;
+    d.g = f->geo();
+    return d;
+}
+
+static int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Build or rebuild the device tables of a plan for the given fields.
+static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, int phase_block, int remap,
+                          int out_cap, hipStream_t st)
+{
+    const bool shape_change = p.nlat != (int)fs.size();
+    if (shape_change) p.release();
+    p.nlat = (int)fs.size();
+    p.prec = fs[0]->prec;
+    p.phase_block = phase_block;
+    p.remap = remap;
+    p.host_descs.clear();
+    p.bbeg_phase_h.assign(1, 0);
+    p.bbeg_link_h.assign(1, 0);
+    p.bbeg_site_h.assign(1, 0);
+    for (auto* f : fs) {
+        p.host_descs.push_back(base_desc(f));
+        p.bbeg_phase_h.push_back(p.bbeg_phase_h.back() + ceil_div(f->Vh, phase_block));
+        p.bbeg_link_h.push_back(p.bbeg_link_h.back() + ceil_div(8LL * f->Vh, 256));
+        p.bbeg_site_h.push_back(p.bbeg_site_h.back() + ceil_div(2LL * f->Vh, 256));
+    }
+    p.nblk_phase = p.bbeg_phase_h.back();
+    p.nblk_link = p.bbeg_link_h.back();
+    p.nblk_site = p.bbeg_site_h.back();
+    if (!p.d_descs) {
+        HIPCHK(hipMalloc(&p.d_descs, sizeof(LatDesc) * p.nlat));
+        HIPCHK(hipMalloc(&p.d_bbeg_phase, sizeof(int) * (p.nlat + 1)));
+        HIPCHK(hipMalloc(&p.d_bbeg_link, sizeof(int) * (p.nlat + 1)));
+        HIPCHK(hipMalloc(&p.d_bbeg_site, sizeof(int) * (p.nlat + 1)));
+        HIPCHK(hipMalloc(&p.d_partials, sizeof(double) * std::max(p.nblk_site, p.nblk_link)));
+        HIPCHK(hipMalloc(&p.d_sweep, sizeof(uint64_t)));
+        HIPCHK(hipMalloc(&p.d_exh, sizeof(unsigned long long)));
+    }
+    if (out_cap > p.out_cap) {
+        hipFree(p.d_out);
+        p.d_out = nullptr;
+        HIPCHK(hipMalloc(&p.d_out, sizeof(double) * out_cap));
+        p.out_cap = out_cap;
+    }
+    HIPCHK(upload_descs(p.d_descs, p.host_descs, st));
+    HIPCHK(upload_ints(p.d_bbeg_phase, p.bbeg_phase_h, st));
+    HIPCHK(upload_ints(p.d_bbeg_link, p.bbeg_link_h, st));
+    HIPCHK(upload_ints(p.d_bbeg_site, p.bbeg_site_h, st));
+    return SU3_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch configuration, autotuning and profiling state.
+// ---------------------------------------------------------------------------
+static std::mutex g_mu;
+static int g_forced_block = 0, g_forced_remap = 1;
+static bool g_autotune = false;
+static std::map<std::string, std::pair<int, int>> g_tuned;
+static bool g_profile = false;
+static double g_prof_ms[2] = { 0, 0 };
+static long long g_prof_n[2] = { 0, 0 };
+static std::vector<hipEvent_t> g_events;
+
+static std::string shape_key(const std::vector<su3_field_s*>& fs)
+{
+    std::string k = std::to_string(fs[0]->prec);
+    for (auto* f : fs) k += ":" + std::to_string(f->L[0]) + "x" + std::to_string(f->L[1]) + "x" +
+                            std::to_string(f->L[2]) + "x" + std::to_string(f->L[3]);
+    return k;
+}
+
+static void launch_choice(const std::vector<su3_field_s*>& fs, int& block, int& remap)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_forced_block > 0) {
+        block = g_forced_block;
+        remap = g_forced_remap;
+        return;
+    }
+    auto it = g_tuned.find(shape_key(fs));
+    if (it != g_tuned.end()) {
+        block = it->second.first;
+        remap = it->second.second;
+        return;
+    }
+    block = 256;
+    remap = 1;
+}
+
+static int32_t ensure_events(size_t n)
+{
+    while (g_events.size() < n) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        g_events.push_back(e);
+    }
+    return SU3_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The sweep schedule, shared by the eager single-lattice path, the graph
+// capture of batches and the autotuner.  Enqueues n_sweeps sweeps on st.
+// ---------------------------------------------------------------------------
+struct SweepOpts {
+    int n_or, n_hits, max_tries, reunit_every, sampler;
+    bool record;
+};
+
+static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, hipStream_t st,
+                              std::vector<std::pair<int, int>>* prof_marks)
+{
+    const Grid gph = p.grid_phase();
+    const HbArgs hb{ o.n_hits, o.max_tries, o.sampler };
+    for (int k = 0; k < n_sweeps; k++) {
+        for (int pass = 0; pass <= o.n_or; pass++) {
+            const int kind = pass == 0 ? 0 : 1;
+            for (int mu = 0; mu < 4; mu++)
+                for (int par = 0; par < 2; par++) {
+                    int ev = -1;
+                    if (prof_marks) {
+                        ev = (int)prof_marks->size() * 2;
+                        int32_t rc = ensure_events((size_t)ev + 2);
+                        if (rc) return rc;
+                        HIPCHK(hipEventRecord(g_events[ev], st));
+                    }
+                    HIPCHK(launch_phase(p.prec, kind, gph, mu, par, p.d_sweep, k, hb, kind == 0 ? p.d_exh : nullptr,
+                                        st));
+                    if (prof_marks) {
+                        HIPCHK(hipEventRecord(g_events[ev + 1], st));
+                        prof_marks->push_back({ ev, kind });
+                    }
+                }
+        }
+        if (o.reunit_every > 0) HIPCHK(launch_reunit(p.prec, p.grid_link(), p.d_sweep, k, o.reunit_every, st));
+        if (o.record) {
+            HIPCHK(launch_plaq_partial(p.prec, p.grid_site(), p.d_partials, st));
+            HIPCHK(launch_reduce_final(p.grid_site(), p.d_partials, p.d_out, 1, k * p.nlat, st));
+        }
+    }
+    return SU3_OK;
+}
+
+static int32_t validate_hb(const su3_hb_params* pp, SweepOpts& o)
+{
+    su3_hb_params d{ 4, 1, 64, 0, SU3_SAMPLER_KP };
+    const su3_hb_params& p = pp ? *pp : d;
+    if (p.n_or < 0 || p.n_or > 1000) return fail(SU3_ERR_ARG, "n_or must be in [0, 1000]");
+    if (p.n_hb_hits < 1 || p.n_hb_hits > 255) return fail(SU3_ERR_ARG, "n_hb_hits must be in [1, 255]");
+    if (p.hb_max_tries < 1 || p.hb_max_tries > 4096) return fail(SU3_ERR_ARG, "hb_max_tries must be in [1, 4096]");
+    if (p.reunit_every < 0) return fail(SU3_ERR_ARG, "reunit_every must be >= 0");
+    if (p.sampler != SU3_SAMPLER_KP && p.sampler != SU3_SAMPLER_CREUTZ) return fail(SU3_ERR_ARG, "unknown sampler");
+    o.n_or = p.n_or;
+    o.n_hits = p.n_hb_hits;
+    o.max_tries = p.hb_max_tries;
+    o.reunit_every = p.reunit_every;
+    o.sampler = p.sampler;
+    return SU3_OK;
+}
+
+// Time each launch shape on scratch copies (hot starts) of the given shapes
+// and remember the fastest for this shape set.
+static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
+{
+    std::vector<su3_field_s> scratch(fs.size());
+    std::vector<su3_field_s*> sp;
+    int32_t rc = SU3_OK;
+    for (size_t i = 0; i < fs.size(); i++) {
+        scratch[i] = *fs[i];
+        scratch[i].data = nullptr;
+        scratch[i].owned = true;
+        scratch[i].plan_ready = false;
+        scratch[i].plan = Plan();
+        if (hipMalloc(&scratch[i].data, fs[i]->bytes) != hipSuccess) {
+            rc = fail(SU3_ERR_NOMEM, "autotune scratch allocation failed");
+            break;
+        }
+        sp.push_back(&scratch[i]);
+    }
+    Plan p;
+    const int blocks[] = { 64, 128, 256, 512 };
+    float best = 1e30f;
+    int bb = 256, br = 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(SU3_ERR_HIP, "event creation failed");
+    for (int bi = 0; bi < 4 && !rc; bi++)
+        for (int remap = 0; remap < 2 && !rc; remap++) {
+            rc = plan_build(p, sp, blocks[bi], remap, 1, st);
+            if (rc) break;
+            if (bi == 0 && remap == 0) {
+                for (size_t i = 0; i < sp.size(); i++) p.host_descs[i].seed = 12345u + (uint32_t)i;
+                if (upload_descs(p.d_descs, p.host_descs, st) != hipSuccess ||
+                    launch_init(p.prec, 1, p.grid_link(), st) != hipSuccess) {
+                    rc = fail(SU3_ERR_HIP, "autotune init failed");
+                    break;
+                }
+            }
+            k_set_u64<<<1, 1, 0, st>>>(p.d_sweep, 0);
+            SweepOpts o{ 1, 1, 64, 0, 0, false };
+            rc = enqueue_sweeps(p, 1, o, st, nullptr);  // warm-up
+            if (rc) break;
+            hipEventRecord(e0, st);
+            rc = enqueue_sweeps(p, 2, o, st, nullptr);
+            if (rc) break;
+            hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(SU3_ERR_HIP, "autotune timing failed");
+                break;
+            }
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                bb = blocks[bi];
+                br = remap;
+            }
+        }
+    hipStreamSynchronize(st);
+    p.release();
+    for (auto& s : scratch) hipFree(s.data);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned[shape_key(fs)] = { bb, br };
+    return SU3_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graph cache for batched sweeps.
+// ---------------------------------------------------------------------------
+struct GraphEntry {
+    std::string key;
+    std::vector<su3_field_s*> fields;
+    Plan plan;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t capture = nullptr;
+};
+static std::vector<GraphEntry*> g_graphs;
+
+static void drop_graph(GraphEntry* g)
+{
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->capture) hipStreamDestroy(g->capture);
+    g->plan.release();
+    delete g;
+}
+
+static void forget_field_graphs(su3_field_s* f)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (size_t i = 0; i < g_graphs.size();) {
+        GraphEntry* g = g_graphs[i];
+        if (std::find(g->fields.begin(), g->fields.end(), f) != g->fields.end()) {
+            hipStreamSynchronize(f->stream);
+            drop_graph(g);
+            g_graphs.erase(g_graphs.begin() + i);
+        } else {
+            i++;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host Philox (for the Metropolis test) -- the same generator as on device.
+// ---------------------------------------------------------------------------
+static void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, y1 = (uint32_t)p1;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1, y3 = (uint32_t)p0;
+        c[0] = y0;
+        c[1] = y1;
+        c[2] = y2;
+        c[3] = y3;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Single-field helpers
+// ---------------------------------------------------------------------------
+static int32_t single_plan(su3_field_s* f, int out_cap)
+{
+    int block, remap;
+    std::vector<su3_field_s*> fs{ f };
+    launch_choice(fs, block, remap);
+    if (!f->plan_ready || f->plan.phase_block != block || f->plan.remap != remap || f->plan.out_cap < out_cap ||
+        f->plan.host_descs.empty() || f->plan.host_descs[0].aux != f->aux8 ||
+        f->plan.host_descs[0].aux2 != f->alt[0]) {
+        int32_t rc = plan_build(f->plan, fs, block, remap, std::max(out_cap, 8), f->stream);
+        if (rc) return rc;
+        f->plan_ready = true;
+    }
+    return SU3_OK;
+}
+
+static int32_t ensure_scratch(su3_field_s* f, bool alts, bool aux)
+{
+    if (alts && !f->alt[1]) {
+        for (int k = 0; k < 2; k++)
+            if (!f->alt[k] && hipMalloc(&f->alt[k], f->bytes) != hipSuccess)
+                return fail(SU3_ERR_NOMEM, "scratch field allocation failed");
+    }
+    if (aux && !f->aux8 && hipMalloc(&f->aux8, f->bytes8) != hipSuccess)
+        return fail(SU3_ERR_NOMEM, "momentum buffer allocation failed");
+    if (!f->d_extra && hipMalloc(&f->d_extra, sizeof(LatDesc) * 8) != hipSuccess)
+        return fail(SU3_ERR_NOMEM, "descriptor allocation failed");
+    f->plan_ready = false;  // descriptors carry the scratch pointers
+    return SU3_OK;
+}
+
+// result = sum over sites of [1 - (1/3) Re Tr U_p] using descriptor d (on device)
+static int32_t action_density_sum(su3_field_s* f, const LatDesc* d, double* out)
+{
+    Plan& p = f->plan;
+    HIPCHK(launch_plaq_partial(f->prec, p.grid_site(d), p.d_partials, f->stream));
+    HIPCHK(launch_reduce_final(p.grid_site(d), p.d_partials, p.d_out, 1, 0, f->stream));
+    HIPCHK(hipMemcpyAsync(out, p.d_out, sizeof(double), hipMemcpyDeviceToHost, f->stream));
+    HIPCHK(hipStreamSynchronize(f->stream));
+    return SU3_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* su3_last_error(void) { return g_err.c_str(); }
+
+int32_t su3_field_bytes(const int32_t dims[4], int32_t prec, size_t* out)
+{
+    int32_t rc = check_dims(dims);
+    if (rc) return rc;
+    if (prec < 0 || prec > 2) return fail(SU3_ERR_ARG, "unknown precision");
+    if (!out) return fail(SU3_ERR_ARG, "out is NULL");
+    size_t cs, cs8, b, b8;
+    layout(dims, prec, cs, cs8, b, b8);
+    *out = b;
+    return SU3_OK;
+}
+
+static int32_t make_field(const int32_t dims[4], int32_t prec, void* ptr, size_t nbytes, bool own, void* stream,
+                          su3_field* out)
+{
+    int32_t rc = check_dims(dims);
+    if (rc) return rc;
+    if (prec < 0 || prec > 2) return fail(SU3_ERR_ARG, "unknown precision");
+    if (!out) return fail(SU3_ERR_ARG, "out is NULL");
+    su3_field_s* f = new su3_field_s();
+    for (int m = 0; m < 4; m++) f->L[m] = dims[m];
+    f->V = dims[0] * dims[1] * dims[2] * dims[3];
+    f->Vh = f->V / 2;
+    f->prec = prec;
+    f->NC = prec_ncomp(prec);
+    layout(dims, prec, f->cs, f->cs8, f->bytes, f->bytes8);
+    f->stream = (hipStream_t)stream;
+    if (own) {
+        if (hipMalloc(&f->data, f->bytes) != hipSuccess) {
+            delete f;
+            return fail(SU3_ERR_NOMEM, "field allocation of " + std::to_string(f->bytes) + " bytes failed");
+        }
+        f->owned = true;
+    } else {
+        if (!ptr) {
+            delete f;
+            return fail(SU3_ERR_ARG, "dev_ptr is NULL");
+        }
+        if (nbytes < f->bytes) {
+            size_t need = f->bytes;
+            delete f;
+            return fail(SU3_ERR_ARG, "wrapped buffer too small: need " + std::to_string(need) + " bytes");
+        }
+        if (((uintptr_t)ptr) & 255) {
+            delete f;
+            return fail(SU3_ERR_ARG, "wrapped buffer must be 256-byte aligned");
+        }
+        f->data = ptr;
+        f->owned = false;
+    }
+    *out = f;
+    return SU3_OK;
+}
+
+int32_t su3_field_create(const int32_t dims[4], int32_t prec, void* hip_stream, su3_field* out)
+{
+    return make_field(dims, prec, nullptr, 0, true, hip_stream, out);
+}
+
+int32_t su3_field_wrap(const int32_t dims[4], int32_t prec, void* dev_ptr, size_t bytes, void* hip_stream,
+                       su3_field* out)
+{
+    return make_field(dims, prec, dev_ptr, bytes, false, hip_stream, out);
+}
+
+int32_t su3_field_destroy(su3_field f)
+{
+    if (!f) return SU3_OK;
+    forget_field_graphs(f);
+    hipStreamSynchronize(f->stream);
+    f->plan.release();
+    if (f->owned) hipFree(f->data);
+    hipFree(f->alt[0]);
+    hipFree(f->alt[1]);
+    hipFree(f->aux8);
+    hipFree(f->d_extra);
+    delete f;
+    return SU3_OK;
+}
+
+int32_t su3_field_set_stream(su3_field f, void* hip_stream)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    f->stream = (hipStream_t)hip_stream;
+    return SU3_OK;
+}
+
+int32_t su3_field_info(su3_field f, int32_t dims[4], int32_t* prec, size_t* bytes)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (dims)
+        for (int m = 0; m < 4; m++) dims[m] = f->L[m];
+    if (prec) *prec = f->prec;
+    if (bytes) *bytes = f->bytes;
+    return SU3_OK;
+}
+
+int32_t su3_init_cold(su3_field f)
+{
+    int32_t rc = check_field(f);
+    if (!rc) rc = single_plan(f, 1);
+    if (rc) return rc;
+    HIPCHK(launch_init(f->prec, 0, f->plan.grid_link(), f->stream));
+    return SU3_OK;
+}
+
+int32_t su3_init_hot(su3_field f, uint32_t seed, uint32_t lattice_id)
+{
+    int32_t rc = check_field(f);
+    if (!rc) rc = single_plan(f, 1);
+    if (rc) return rc;
+    std::vector<LatDesc> d{ base_desc(f) };
+    d[0].seed = seed;
+    d[0].lid = lattice_id;
+    HIPCHK(upload_descs(f->plan.d_descs, d, f->stream));
+    HIPCHK(launch_init(f->prec, 1, f->plan.grid_link(), f->stream));
+    return SU3_OK;
+}
+
+int32_t su3_field_to_host(su3_field f, double* out)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!out) return fail(SU3_ERR_ARG, "out is NULL");
+    const size_t n = (size_t)f->V * 72 * sizeof(double);
+    double* stage = nullptr;
+    HIPCHK(hipMalloc(&stage, n));
+    hipError_t e = launch_to_aos(f->prec, nullptr, f->geo(), f->data, f->cs, stage, f->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, stage, n, hipMemcpyDeviceToHost, f->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+    hipFree(stage);
+    if (e != hipSuccess) return fail(SU3_ERR_HIP, std::string("to_host: ") + hipGetErrorString(e));
+    return SU3_OK;
+}
+
+int32_t su3_field_from_host(su3_field f, const double* in)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!in) return fail(SU3_ERR_ARG, "in is NULL");
+    const size_t n = (size_t)f->V * 72 * sizeof(double);
+    double* stage = nullptr;
+    HIPCHK(hipMalloc(&stage, n));
+    hipError_t e = hipMemcpyAsync(stage, in, n, hipMemcpyHostToDevice, f->stream);
+    if (e == hipSuccess) e = launch_from_aos(f->prec, f->geo(), f->data, f->cs, stage, f->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+    hipFree(stage);
+    if (e != hipSuccess) return fail(SU3_ERR_HIP, std::string("from_host: ") + hipGetErrorString(e));
+    return SU3_OK;
+}
+
+int32_t su3_field_copy(su3_field dst, su3_field src)
+{
+    int32_t rc = check_field(dst);
+    if (!rc) rc = check_field(src);
+    if (rc) return rc;
+    for (int m = 0; m < 4; m++)
+        if (dst->L[m] != src->L[m]) return fail(SU3_ERR_SHAPE, "copy between fields of different shapes");
+    if (dst->stream != src->stream) HIPCHK(hipStreamSynchronize(src->stream));
+    HIPCHK(launch_convert(dst->prec, dst->data, dst->cs, src->prec, src->data, src->cs, src->Vh, dst->stream));
+    return SU3_OK;
+}
+
+int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattice_id, uint64_t first_sweep,
+                        int32_t n_sweeps, const su3_hb_params* pp, double* plaq_hist)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    SweepOpts o;
+    if ((rc = validate_hb(pp, o))) return rc;
+    if (n_sweeps < 0) return fail(SU3_ERR_ARG, "n_sweeps must be >= 0");
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(SU3_ERR_ARG, "beta must be finite and >= 0");
+    o.record = plaq_hist != nullptr;
+    if (g_autotune) {
+        std::vector<su3_field_s*> fs{ f };
+        bool have;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            have = g_tuned.count(shape_key(fs)) > 0;
+        }
+        if (!have && (rc = autotune(fs, f->stream))) return rc;
+    }
+    if ((rc = single_plan(f, std::max(1, n_sweeps)))) return rc;
+    Plan& p = f->plan;
+    std::vector<LatDesc> d{ base_desc(f) };
+    d[0].beta = beta;
+    d[0].seed = seed;
+    d[0].lid = lattice_id;
+    HIPCHK(upload_descs(p.d_descs, d, f->stream));
+    k_set_u64<<<1, 1, 0, f->stream>>>(p.d_sweep, first_sweep);
+    k_set_u64<<<1, 1, 0, f->stream>>>((uint64_t*)p.d_exh, 0);
+    HIPCHK(hipGetLastError());
+    std::vector<std::pair<int, int>> marks;
+    const bool prof = g_profile;
+    if ((rc = enqueue_sweeps(p, n_sweeps, o, f->stream, prof ? &marks : nullptr))) return rc;
+    unsigned long long ex = 0;
+    HIPCHK(hipMemcpyAsync(&ex, p.d_exh, sizeof ex, hipMemcpyDeviceToHost, f->stream));
+    std::vector<double> h;
+    if (o.record && n_sweeps > 0) {
+        h.resize(n_sweeps);
+        HIPCHK(hipMemcpyAsync(h.data(), p.d_out, sizeof(double) * n_sweeps, hipMemcpyDeviceToHost, f->stream));
+    }
+    HIPCHK(hipStreamSynchronize(f->stream));
+    f->last_exhausted = (int64_t)ex;
+    for (int k = 0; k < (int)h.size(); k++) plaq_hist[k] = 1.0 - h[k] / (6.0 * f->V);
+    if (prof) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& m : marks) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, g_events[m.first], g_events[m.first + 1]));
+            g_prof_ms[m.second] += ms;
+            g_prof_n[m.second] += 1;
+        }
+    }
+    return SU3_OK;
+}
+
+int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* betas, const uint32_t* seeds,
+                              const uint32_t* lattice_ids, uint64_t first_sweep, int32_t n_sweeps,
+                              const su3_hb_params* pp, double* plaq_out)
+{
+    if (!fs || n <= 0) return fail(SU3_ERR_ARG, "need at least one field");
+    if (!betas || !seeds || !lattice_ids) return fail(SU3_ERR_ARG, "betas, seeds and lattice_ids are required");
+    if (n_sweeps < 0) return fail(SU3_ERR_ARG, "n_sweeps must be >= 0");
+    SweepOpts o;
+    int32_t rc = validate_hb(pp, o);
+    if (rc) return rc;
+    o.record = plaq_out != nullptr;
+    std::vector<su3_field_s*> v;
+    for (int i = 0; i < n; i++) {
+        if (!fs[i]) return fail(SU3_ERR_ARG, "NULL field in batch");
+        if (fs[i]->prec != fs[0]->prec) return fail(SU3_ERR_UNSUPPORTED, "a batch must share one precision");
+        if (fs[i]->stream != fs[0]->stream) return fail(SU3_ERR_ARG, "a batch must share one stream");
+        if (!(betas[i] >= 0.0) || !std::isfinite(betas[i])) return fail(SU3_ERR_ARG, "beta must be finite and >= 0");
+        for (int j = 0; j < i; j++)
+            if (fs[j] == fs[i]) return fail(SU3_ERR_ARG, "a field appears twice in the batch");
+        v.push_back(fs[i]);
+    }
+    hipStream_t st = fs[0]->stream;
+    if (n_sweeps == 0) return SU3_OK;
+    if (g_autotune) {
+        bool have;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            have = g_tuned.count(shape_key(v)) > 0;
+        }
+        if (!have && (rc = autotune(v, st))) return rc;
+    }
+    int block, remap;
+    launch_choice(v, block, remap);
+    std::string key = std::to_string(n_sweeps) + "|" + std::to_string(o.n_or) + "," + std::to_string(o.n_hits) +
+                      "," + std::to_string(o.max_tries) + "," + std::to_string(o.reunit_every) + "," +
+                      std::to_string(o.sampler) + "," + std::to_string(o.record) + "|" + std::to_string(block) +
+                      "," + std::to_string(remap) + "|";
+    for (auto* f : v) {
+        char buf[64];
+        snprintf(buf, sizeof buf, "%p,", (void*)f);
+        key += buf;
+    }
+    const bool prof = g_profile;
+    if (prof) key += "eager";
+    GraphEntry* ge = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto* g : g_graphs)
+            if (g->key == key) ge = g;
+    }
+    if (!ge && prof) {
+        ge = new GraphEntry();
+        ge->key = key;
+        ge->fields = v;
+        rc = plan_build(ge->plan, v, block, remap, n_sweeps * n, st);
+        if (rc) {
+            drop_graph(ge);
+            return rc;
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_graphs.push_back(ge);
+    }
+    if (!ge) {
+        ge = new GraphEntry();
+        ge->key = key;
+        ge->fields = v;
+        rc = plan_build(ge->plan, v, block, remap, n_sweeps * n, st);
+        if (!rc && hipStreamCreateWithFlags(&ge->capture, hipStreamNonBlocking) != hipSuccess)
+            rc = fail(SU3_ERR_HIP, "capture stream creation failed");
+        if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(SU3_ERR_HIP, "stream sync failed");
+        if (!rc) {
+            if (hipStreamBeginCapture(ge->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                rc = fail(SU3_ERR_HIP, "graph capture could not start");
+            } else {
+                int32_t erc = enqueue_sweeps(ge->plan, n_sweeps, o, ge->capture, nullptr);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(ge->capture, &g);
+                ge->graph = g;
+                if (erc)
+                    rc = erc;
+                else if (e != hipSuccess || !g)
+                    rc = fail(SU3_ERR_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+                else if (hipGraphInstantiate(&ge->exec, g, nullptr, nullptr, 0) != hipSuccess)
+                    rc = fail(SU3_ERR_HIP, "graph instantiation failed");
+            }
+        }
+        if (rc) {
+            drop_graph(ge);
+            return rc;
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (g_graphs.size() >= 16) {
+            drop_graph(g_graphs.front());
+            g_graphs.erase(g_graphs.begin());
+        }
+        g_graphs.push_back(ge);
+    }
+    Plan& p = ge->plan;
+    for (int i = 0; i < n; i++) {
+        p.host_descs[i] = base_desc(v[i]);
+        p.host_descs[i].beta = betas[i];
+        p.host_descs[i].seed = seeds[i];
+        p.host_descs[i].lid = lattice_ids[i];
+    }
+    HIPCHK(upload_descs(p.d_descs, p.host_descs, st));
+    k_set_u64<<<1, 1, 0, st>>>(p.d_sweep, first_sweep);
+    k_set_u64<<<1, 1, 0, st>>>((uint64_t*)p.d_exh, 0);
+    HIPCHK(hipGetLastError());
+    std::vector<std::pair<int, int>> marks;
+    if (prof) {
+        if ((rc = enqueue_sweeps(p, n_sweeps, o, st, &marks))) return rc;
+    } else {
+        HIPCHK(hipGraphLaunch(ge->exec, st));
+    }
+    unsigned long long ex = 0;
+    HIPCHK(hipMemcpyAsync(&ex, p.d_exh, sizeof ex, hipMemcpyDeviceToHost, st));
+    std::vector<double> h;
+    if (o.record) {
+        h.resize((size_t)n_sweeps * n);
+        HIPCHK(hipMemcpyAsync(h.data(), p.d_out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (auto* f : v) f->last_exhausted = 0;
+    v[0]->last_exhausted = (int64_t)ex;
+    if (o.record)
+        for (int k = 0; k < n_sweeps; k++)
+            for (int i = 0; i < n; i++) plaq_out[(size_t)k * n + i] = 1.0 - h[(size_t)k * n + i] / (6.0 * v[i]->V);
+    if (prof) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& mk : marks) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, g_events[mk.first], g_events[mk.first + 1]));
+            g_prof_ms[mk.second] += ms;
+            g_prof_n[mk.second] += 1;
+        }
+    }
+    return SU3_OK;
+}
+
+int32_t su3_last_exhausted(su3_field f, int64_t* count)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!count) return fail(SU3_ERR_ARG, "count is NULL");
+    *count = f->last_exhausted;
+    return SU3_OK;
+}
+
+int32_t su3_plaquette(su3_field f, double* out)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!out) return fail(SU3_ERR_ARG, "out is NULL");
+    if ((rc = single_plan(f, 1))) return rc;
+    double s = 0;
+    if ((rc = action_density_sum(f, f->plan.d_descs, &s))) return rc;
+    *out = 1.0 - s / (6.0 * f->V);
+    return SU3_OK;
+}
+
+int32_t su3_action(su3_field f, double beta, double* out)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!out) return fail(SU3_ERR_ARG, "out is NULL");
+    if ((rc = single_plan(f, 1))) return rc;
+    double s = 0;
+    if ((rc = action_density_sum(f, f->plan.d_descs, &s))) return rc;
+    *out = beta * s;
+    return SU3_OK;
+}
+
+static int32_t scalar_reduction(su3_field f, int which, double* out)
+{
+    int32_t rc = single_plan(f, 1);
+    if (rc) return rc;
+    Plan& p = f->plan;
+    if (which == 0)
+        HIPCHK(launch_qtop_partial(f->prec, p.grid_site(), p.d_partials, f->stream));
+    else
+        HIPCHK(launch_energy_partial(f->prec, p.grid_site(), p.d_partials, f->stream));
+    HIPCHK(launch_reduce_final(p.grid_site(), p.d_partials, p.d_out, 1, 0, f->stream));
+    HIPCHK(hipMemcpyAsync(out, p.d_out, sizeof(double), hipMemcpyDeviceToHost, f->stream));
+    HIPCHK(hipStreamSynchronize(f->stream));
+    return SU3_OK;
+}
+
+int32_t su3_topological_charge(su3_field f, double* Q)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!Q) return fail(SU3_ERR_ARG, "Q is NULL");
+    return scalar_reduction(f, 0, Q);
+}
+
+int32_t su3_clover_energy(su3_field f, double* E)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!E) return fail(SU3_ERR_ARG, "E is NULL");
+    rc = scalar_reduction(f, 1, E);
+    if (!rc) *E /= f->V;
+    return rc;
+}
+
+int32_t su3_reunitarize(su3_field f)
+{
+    int32_t rc = check_field(f);
+    if (!rc) rc = single_plan(f, 1);
+    if (rc) return rc;
+    HIPCHK(launch_reunit(f->prec, f->plan.grid_link(), f->plan.d_sweep, 0, 0, f->stream));
+    return SU3_OK;
+}
+
+int32_t su3_gauge_transform(su3_field f, uint32_t seed)
+{
+    int32_t rc = check_field(f);
+    if (!rc) rc = single_plan(f, 1);
+    if (rc) return rc;
+    HIPCHK(launch_gauge(f->prec, f->plan.grid_link(), seed, f->stream));
+    return SU3_OK;
+}
+
+int32_t su3_check_field(su3_field f, double tol, double* max_dev, int64_t* worst)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    const int nb = ceil_div(8LL * f->Vh, 256);
+    double* bm = nullptr;
+    int* ba = nullptr;
+    HIPCHK(hipMalloc(&bm, sizeof(double) * nb));
+    if (hipMalloc(&ba, sizeof(int) * nb) != hipSuccess) {
+        hipFree(bm);
+        return fail(SU3_ERR_NOMEM, "check buffers");
+    }
+    std::vector<double> hm(nb);
+    std::vector<int> ha(nb);
+    hipError_t e = launch_check(f->prec, f->geo(), f->data, f->cs, bm, ba, nb, f->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hm.data(), bm, sizeof(double) * nb, hipMemcpyDeviceToHost, f->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ha.data(), ba, sizeof(int) * nb, hipMemcpyDeviceToHost, f->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+    hipFree(bm);
+    hipFree(ba);
+    if (e != hipSuccess) return fail(SU3_ERR_HIP, std::string("check: ") + hipGetErrorString(e));
+    double best = -1;
+    int64_t arg = -1;
+    for (int b = 0; b < nb; b++)
+        if (hm[b] > best) {
+            best = hm[b];
+            arg = ha[b];
+        }
+    if (max_dev) *max_dev = best;
+    if (worst) *worst = arg;
+    if (!(best <= tol))
+        return fail(SU3_ERR_NUMERIC, "link " + std::to_string(arg) + " deviates from SU(3) by " + std::to_string(best));
+    return SU3_OK;
+}
+
+int32_t su3_hmc_trajectory(su3_field f, double beta, double tau, int32_t n_steps, uint32_t seed, uint32_t lattice_id,
+                           uint64_t traj, int32_t metropolis, double* dH, int32_t* accepted)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (n_steps < 1) return fail(SU3_ERR_ARG, "n_steps must be >= 1");
+    if (!std::isfinite(tau) || !std::isfinite(beta) || beta < 0) return fail(SU3_ERR_ARG, "tau and beta must be finite, beta >= 0");
+    if ((rc = ensure_scratch(f, true, true))) return rc;
+    if ((rc = single_plan(f, 4))) return rc;
+    Plan& p = f->plan;
+    hipStream_t st = f->stream;
+    // descriptor variants: 0: U -> alt0, 1: alt0 -> alt1, 2: alt1 -> alt0
+    std::vector<LatDesc> d(3, base_desc(f));
+    for (auto& x : d) {
+        x.beta = beta;
+        x.seed = seed;
+        x.lid = lattice_id;
+        x.aux = f->aux8;
+    }
+    d[0].U = f->data;
+    d[0].aux2 = f->alt[0];
+    d[1].U = f->alt[0];
+    d[1].aux2 = f->alt[1];
+    d[2].U = f->alt[1];
+    d[2].aux2 = f->alt[0];
+    HIPCHK(upload_descs(f->d_extra, d, st));
+    const Grid g0 = p.grid_link(f->d_extra + 0);
+    HIPCHK(launch_mom_refresh(f->prec, g0, traj, st));
+    // H0
+    double K0 = 0, S0 = 0;
+    HIPCHK(launch_kinetic_partial(f->prec, g0, p.d_partials, st));
+    HIPCHK(launch_reduce_final(g0, p.d_partials, p.d_out, 1, 0, st));
+    HIPCHK(launch_plaq_partial(f->prec, p.grid_site(f->d_extra + 0), p.d_partials, st));
+    HIPCHK(launch_reduce_final(p.grid_site(f->d_extra + 0), p.d_partials, p.d_out, 1, 1, st));
+    const double eps = tau / n_steps;
+    int cur = 0;  // descriptor whose U holds the current links
+    for (int k = 0; k < n_steps; k++) {
+        const double ek = (k == 0) ? 0.5 * eps : eps;
+        HIPCHK(launch_kick_drift(f->prec, p.grid_link(f->d_extra + cur), ek, eps, 1, st));
+        cur = (cur == 1) ? 2 : 1;
+    }
+    HIPCHK(launch_kick_drift(f->prec, p.grid_link(f->d_extra + cur), 0.5 * eps, 0.0, 0, st));
+    HIPCHK(launch_kinetic_partial(f->prec, g0, p.d_partials, st));
+    HIPCHK(launch_reduce_final(g0, p.d_partials, p.d_out, 1, 2, st));
+    HIPCHK(launch_plaq_partial(f->prec, p.grid_site(f->d_extra + cur), p.d_partials, st));
+    HIPCHK(launch_reduce_final(p.grid_site(f->d_extra + cur), p.d_partials, p.d_out, 1, 3, st));
+    double r[4];
+    HIPCHK(hipMemcpyAsync(r, p.d_out, sizeof r, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    K0 = r[0];
+    S0 = beta * r[1];
+    const double H0 = K0 + S0, H1 = r[2] + beta * r[3];
+    const double dh = H1 - H0;
+    int acc = 1;
+    if (metropolis) {
+        uint32_t c[4] = { 0u, (uint32_t)P_ACCEPT << 28, (uint32_t)traj, (uint32_t)(traj >> 32) };
+        philox_host(c, seed, lattice_id);
+        const double u = ((double)(c[0] >> 9) * 2.0 + 1.0) * 0x1p-24;
+        acc = (u < std::exp(-dh)) ? 1 : 0;
+    }
+    if (acc) {
+        void* src = (cur == 1) ? f->alt[0] : f->alt[1];
+        HIPCHK(hipMemcpyAsync(f->data, src, f->bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if (dH) *dH = dh;
+    if (accepted) *accepted = acc;
+    return SU3_OK;
+}
+
+int32_t su3_wilson_flow(su3_field f, double eps, int32_t n_steps)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (n_steps < 0) return fail(SU3_ERR_ARG, "n_steps must be >= 0");
+    if (!std::isfinite(eps)) return fail(SU3_ERR_ARG, "eps must be finite");
+    if (n_steps == 0) return SU3_OK;
+    if ((rc = ensure_scratch(f, true, true))) return rc;
+    if ((rc = single_plan(f, 1))) return rc;
+    hipStream_t st = f->stream;
+    std::vector<LatDesc> d(2, base_desc(f));
+    d[0].U = f->data;
+    d[0].aux2 = f->alt[0];
+    d[1].U = f->alt[0];
+    d[1].aux2 = f->data;
+    for (auto& x : d) x.aux = f->aux8;
+    HIPCHK(upload_descs(f->d_extra + 3, d, st));
+    const double cz[3] = { 0.25, 8.0 / 9.0, 0.75 };
+    const double ca[3] = { 0.0, -17.0 / 9.0, -1.0 };
+    int cur = 0;
+    for (int s = 0; s < n_steps; s++)
+        for (int k = 0; k < 3; k++) {
+            HIPCHK(launch_flow_stage(f->prec, f->plan.grid_link(f->d_extra + 3 + cur), eps, cz[k], ca[k], k == 0, st));
+            cur ^= 1;
+        }
+    if (cur == 1) HIPCHK(hipMemcpyAsync(f->data, f->alt[0], f->bytes, hipMemcpyDeviceToDevice, st));
+    return SU3_OK;
+}
+
+int32_t su3_restrict(su3_field fine, su3_field coarse)
+{
+    int32_t rc = check_field(fine);
+    if (!rc) rc = check_field(coarse);
+    if (rc) return rc;
+    for (int m = 0; m < 4; m++)
+        if (fine->L[m] != 2 * coarse->L[m]) return fail(SU3_ERR_SHAPE, "fine dims must be twice the coarse dims");
+    if (fine->stream != coarse->stream) HIPCHK(hipStreamSynchronize(fine->stream));
+    HIPCHK(launch_restrict(fine->prec, fine->geo(), fine->data, fine->cs, coarse->prec, coarse->geo(), coarse->data,
+                           coarse->cs, coarse->stream));
+    return SU3_OK;
+}
+
+int32_t su3_prolongate(su3_field coarse, su3_field fine, double c, double rel_tol, int32_t max_iter,
+                       int32_t iters_out[3])
+{
+    int32_t rc = check_field(fine);
+    if (!rc) rc = check_field(coarse);
+    if (rc) return rc;
+    for (int m = 0; m < 4; m++)
+        if (fine->L[m] != 2 * coarse->L[m]) return fail(SU3_ERR_SHAPE, "fine dims must be twice the coarse dims");
+    if (!(c > 0) || !std::isfinite(c)) return fail(SU3_ERR_ARG, "c must be > 0");
+    if (!(rel_tol >= 0)) return fail(SU3_ERR_ARG, "rel_tol must be >= 0");
+    if (max_iter < 0) return fail(SU3_ERR_ARG, "max_iter must be >= 0");
+    hipStream_t st = fine->stream;
+    if (coarse->stream != st) HIPCHK(hipStreamSynchronize(coarse->stream));
+    const Geo gf = fine->geo();
+    const size_t csf = padded_stride(fine->Vh, 8);
+    const size_t nbytes = 8 * 18 * csf * 8;
+    double* buf[2] = { nullptr, nullptr };
+    const int nb = ceil_div(2LL * fine->Vh, 256);
+    double* bs = nullptr;
+    if (hipMalloc(&buf[0], nbytes) != hipSuccess || hipMalloc(&buf[1], nbytes) != hipSuccess ||
+        hipMalloc(&bs, sizeof(double) * nb) != hipSuccess) {
+        hipFree(buf[0]);
+        hipFree(buf[1]);
+        hipFree(bs);
+        return fail(SU3_ERR_NOMEM, "prolongation scratch allocation failed");
+    }
+    std::vector<double> hb(nb);
+    auto partial = [&](const double* U, int d, double* out) -> hipError_t {
+        hipError_t e = launch_partial_action(gf, U, csf, d, bs, nb, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hb.data(), bs, sizeof(double) * nb, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        double s = 0;
+        for (int b = 0; b < nb; b++) s += hb[b];
+        *out = s;
+        return e;
+    };
+    hipError_t e = launch_transfer(coarse->prec, coarse->geo(), coarse->data, coarse->cs, gf, buf[0], csf, st);
+    int cur = 0;
+    int iters[3] = { 0, 0, 0 };
+    for (int d = 0; d < 3 && e == hipSuccess; d++) {
+        double s_prev = 0;
+        e = partial(buf[cur], d, &s_prev);
+        int k = 0;
+        while (e == hipSuccess && k < max_iter) {
+            e = launch_ape(gf, buf[cur], buf[cur ^ 1], csf, d, c, st);
+            cur ^= 1;
+            k++;
+            double s = 0;
+            if (e == hipSuccess) e = partial(buf[cur], d, &s);
+            const bool done = std::fabs(s - s_prev) <= rel_tol * s_prev;
+            s_prev = s;
+            if (done) break;
+        }
+        iters[d] = k;
+    }
+    if (e == hipSuccess) e = launch_convert(fine->prec, fine->data, fine->cs, PREC_F64, buf[cur], csf, fine->Vh, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(buf[0]);
+    hipFree(buf[1]);
+    hipFree(bs);
+    if (e != hipSuccess) return fail(SU3_ERR_HIP, std::string("prolongate: ") + hipGetErrorString(e));
+    if (iters_out)
+        for (int d = 0; d < 3; d++) iters_out[d] = iters[d];
+    return SU3_OK;
+}
+
+int32_t su3_set_launch(int32_t block, int32_t xcd_remap)
+{
+    if (!(block == 0 || block == 64 || block == 128 || block == 256 || block == 512))
+        return fail(SU3_ERR_ARG, "block must be 0, 64, 128, 256 or 512");
+    if (xcd_remap != 0 && xcd_remap != 1) return fail(SU3_ERR_ARG, "xcd_remap must be 0 or 1");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_forced_block = block;
+    g_forced_remap = xcd_remap;
+    return SU3_OK;
+}
+
+int32_t su3_get_launch(int32_t* block, int32_t* xcd_remap)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (block) *block = g_forced_block;
+    if (xcd_remap) *xcd_remap = g_forced_remap;
+    return SU3_OK;
+}
+
+int32_t su3_autotune(int32_t enable)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_autotune = enable != 0;
+    return SU3_OK;
+}
+
+int32_t su3_profile_enable(int32_t enable)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_profile = enable != 0;
+    g_prof_ms[0] = g_prof_ms[1] = 0;
+    g_prof_n[0] = g_prof_n[1] = 0;
+    return SU3_OK;
+}
+
+int32_t su3_profile_read(int32_t kind, double* total_ms, int64_t* launches)
+{
+    if (kind != 0 && kind != 1) return fail(SU3_ERR_ARG, "kind must be 0 or 1");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (total_ms) *total_ms = g_prof_ms[kind];
+    if (launches) *launches = g_prof_n[kind];
+    return SU3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,638 @@
+// device.hpp -- device-side building blocks for the SU(3) rethermalization
+// kernels on gfx950: SU(3) matrices in registers, the structure-of-arrays
+// link layout, checkerboard geometry and the Philox4x32-10 generator.
+//
+// Link layout (one allocation per lattice):
+//   element (mu, parity, component, cb) at
+//     base[((mu * 2 + parity) * NC + component) * cs + cb]
+//   NC = 18 (full matrix) or 12 (rows 0 and 1; row 2 rebuilt on load),
+//   component = (row * 3 + col) * 2 + {0: re, 1: im},
+//   cb = checkerboard index = (lexicographic site index) >> 1,
+//   cs = component stride >= V/2, padded so that cs * sizeof(real) is an
+//        odd number of 128-byte lines (component arrays of one link do not
+//        alias in the same L2 sets).
+// Consecutive threads take consecutive cb, so every component load of a
+// wavefront is one contiguous 256 B (fp32) or 512 B (fp64) segment.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msmc {
+
+// ---------------------------------------------------------------------------
+// Lattice geometry.  Site index i = n0 + L0*(n1 + L1*(n2 + L2*n3)); extents
+// are even, so the two sites 2c and 2c+1 have opposite parity and c = i >> 1
+// enumerates each parity exactly once.
+// ---------------------------------------------------------------------------
+struct Geo {
+    int L[4];
+    int h0;   // L0 / 2
+    int Vh;   // sites per parity
+};
+
+__device__ __forceinline__ void cb_coords(const Geo& g, int cb, int par, int n[4])
+{
+    int x0h = cb % g.h0;
+    int r = cb / g.h0;
+    n[1] = r % g.L[1];
+    r /= g.L[1];
+    n[2] = r % g.L[2];
+    n[3] = r / g.L[2];
+    int b = (par + n[1] + n[2] + n[3]) & 1;
+    n[0] = 2 * x0h + b;
+}
+
+__device__ __forceinline__ int lex_index(const Geo& g, const int n[4])
+{
+    return n[0] + g.L[0] * (n[1] + g.L[1] * (n[2] + g.L[2] * n[3]));
+}
+
+__device__ __forceinline__ int wrap_add(int x, int s, int L)
+{
+    x += s;
+    return x < 0 ? x + L : (x >= L ? x - L : x);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the uniform / Gaussian maps.
+// Counter words: c0 = lexicographic site, c1 = purpose<<28 | mu<<24 |
+// subgroup<<20 | hit<<12 | draw, (c2, c3) = 64-bit sweep or trajectory index.
+// Key = (seed, lattice id).
+// ---------------------------------------------------------------------------
+enum Purpose : uint32_t { P_INIT = 1, P_HB = 2, P_HB_DIR = 3, P_MOM = 4, P_ACCEPT = 5, P_GAUGE = 6, P_PARAM = 7 };
+
+__device__ __forceinline__ uint32_t ctr_word(uint32_t purpose, int mu, int sub, int hit, int draw)
+{
+    return (purpose << 28) | ((uint32_t)mu << 24) | ((uint32_t)sub << 20) | ((uint32_t)hit << 12) | (uint32_t)draw;
+}
+
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+template <typename R> __device__ __forceinline__ R u01(uint32_t x);
+template <> __device__ __forceinline__ double u01<double>(uint32_t x)
+{
+    return ((double)(x >> 9) * 2.0 + 1.0) * 0x1p-24;
+}
+template <> __device__ __forceinline__ float u01<float>(uint32_t x)
+{
+    return ((float)(x >> 9) * 2.0f + 1.0f) * 0x1p-24f;
+}
+
+struct Rng {
+    uint32_t k0, k1;
+    uint32_t site;
+    uint64_t step;
+    __device__ __forceinline__ uint4 draw(uint32_t w1) const
+    {
+        return philox10(make_uint4(site, w1, (uint32_t)step, (uint32_t)(step >> 32)), k0, k1);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// fp64 elementary functions of the random draws, each a fixed sequence of
+// IEEE-754 operations (the translation units using them are compiled without
+// floating-point contraction), so the fp64 chain is reproducible bit for bit
+// by any implementation that takes the same steps:
+//  ln x:  x = m 2^e, m in [sqrt(1/2), sqrt(2)), s = (m-1)/(m+1),
+//         ln m = 2 s sum_{k=0..11} s^{2k}/(2k+1) (Horner), ln x = e ln2_hi +
+//         (e ln2_lo + ln m) with the Cody-Waite split of ln 2;
+//  cos, sin of 2 pi u: q = nearest integer to 4u, t = 2 pi (u - q/4) in
+//         [-pi/4, pi/4], Taylor series to t^18 / t^19, q quarter turns;
+//  exp y: n = nearest integer to y/ln2, r = (y - n ln2_hi) - n ln2_lo,
+//         Taylor series to r^17, scaled by 2^n.
+// fp32 uses the device library functions.
+// ---------------------------------------------------------------------------
+struct FixedSeq {
+    static constexpr double ln2_hi = 0x1.62e42feep-1;
+    static constexpr double ln2_lo = 0x1.a39ef35793c76p-33;
+    static constexpr double inv_ln2 = 1.44269504088896340736;
+    static constexpr double two_pi = 6.28318530717958647693;
+    static constexpr double sqrt_half = 0.70710678118654752440;
+};
+
+__device__ __forceinline__ double fact_d(int n)
+{
+    constexpr double F[21] = { 1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0, 40320.0, 362880.0, 3628800.0,
+                               39916800.0, 479001600.0, 6227020800.0, 87178291200.0, 1307674368000.0,
+                               20922789888000.0, 355687428096000.0, 6402373705728000.0,
+                               121645100408832000.0, 2432902008176640000.0 };
+    return F[n];
+}
+
+__device__ __forceinline__ double fs_ln(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < FixedSeq::sqrt_half) {
+        m = 2.0 * m;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+#pragma unroll
+    for (int k = 10; k >= 0; k--) p = p * z + 1.0 / (double)(2 * k + 1);
+    const double de = (double)e;
+    return de * FixedSeq::ln2_hi + (de * FixedSeq::ln2_lo + 2.0 * s * p);
+}
+
+__device__ __forceinline__ void fs_cossin_2pi(double u, double* c, double* s)
+{
+    const double q = floor(4.0 * u + 0.5);
+    const double v = u - 0.25 * q;
+    const double t = FixedSeq::two_pi * v;
+    const double t2 = t * t;
+    double ps = -1.0 / fact_d(19);
+#pragma unroll
+    for (int k = 8; k >= 0; k--) ps = ps * t2 + ((k & 1) ? -1.0 : 1.0) / fact_d(2 * k + 1);
+    double pc = -1.0 / fact_d(18);
+#pragma unroll
+    for (int k = 8; k >= 0; k--) pc = pc * t2 + ((k & 1) ? -1.0 : 1.0) / fact_d(2 * k);
+    const double s0 = t * ps, c0 = pc;
+    switch (((int)q) & 3) {
+    case 0: *c = c0; *s = s0; break;
+    case 1: *c = -s0; *s = c0; break;
+    case 2: *c = -c0; *s = -s0; break;
+    default: *c = s0; *s = -c0; break;
+    }
+}
+
+__device__ __forceinline__ double fs_exp(double y)
+{
+    if (y < -745.0) return 0.0;
+    const double n = floor(y * FixedSeq::inv_ln2 + 0.5);
+    const double r = (y - n * FixedSeq::ln2_hi) - n * FixedSeq::ln2_lo;
+    double p = 1.0 / fact_d(17);
+#pragma unroll
+    for (int k = 16; k >= 0; k--) p = p * r + 1.0 / fact_d(k);
+    return ldexp(p, (int)n);
+}
+
+// math wrappers per precision
+__device__ __forceinline__ double m_log(double x) { return fs_ln(x); }
+__device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_exp(double x) { return fs_exp(x); }
+__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+// (cos 2 pi u, sin 2 pi u)
+__device__ __forceinline__ void m_cossin2pi(double u, double* c, double* s) { fs_cossin_2pi(u, c, s); }
+__device__ __forceinline__ void m_cossin2pi(float u, float* c, float* s) { sincospif(2.0f * u, s, c); }
+__device__ __forceinline__ double m_max(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float m_max(float a, float b) { return fmaxf(a, b); }
+
+// Four normals from one Philox call (Box-Muller on two uniform pairs).
+template <typename R> __device__ __forceinline__ void normals4(uint4 w, R z[4])
+{
+    R u[4] = { u01<R>(w.x), u01<R>(w.y), u01<R>(w.z), u01<R>(w.w) };
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        R r = m_sqrt(R(-2) * m_log(u[2 * h]));
+        R c, s;
+        m_cossin2pi(u[2 * h + 1], &c, &s);
+        z[2 * h] = r * c;
+        z[2 * h + 1] = r * s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 complex matrices in registers, row-major, separate re / im.
+// ---------------------------------------------------------------------------
+template <typename R> struct M3 {
+    R re[9], im[9];
+};
+
+template <typename R> __device__ __forceinline__ void m_set_zero(M3<R>& a)
+{
+#pragma unroll
+    for (int k = 0; k < 9; k++) a.re[k] = a.im[k] = R(0);
+}
+
+template <typename R> __device__ __forceinline__ void m_set_one(M3<R>& a)
+{
+    m_set_zero(a);
+    a.re[0] = a.re[4] = a.re[8] = R(1);
+}
+
+// C = A B
+template <typename R> __device__ __forceinline__ M3<R> m_mul(const M3<R>& a, const M3<R>& b)
+{
+    M3<R> c;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) {
+            R xr = R(0), xi = R(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                xr += a.re[r * 3 + k] * b.re[k * 3 + s] - a.im[r * 3 + k] * b.im[k * 3 + s];
+                xi += a.re[r * 3 + k] * b.im[k * 3 + s] + a.im[r * 3 + k] * b.re[k * 3 + s];
+            }
+            c.re[r * 3 + s] = xr;
+            c.im[r * 3 + s] = xi;
+        }
+    return c;
+}
+
+// C = A B^+
+template <typename R> __device__ __forceinline__ M3<R> m_mul_nd(const M3<R>& a, const M3<R>& b)
+{
+    M3<R> c;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) {
+            R xr = R(0), xi = R(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                xr += a.re[r * 3 + k] * b.re[s * 3 + k] + a.im[r * 3 + k] * b.im[s * 3 + k];
+                xi += a.im[r * 3 + k] * b.re[s * 3 + k] - a.re[r * 3 + k] * b.im[s * 3 + k];
+            }
+            c.re[r * 3 + s] = xr;
+            c.im[r * 3 + s] = xi;
+        }
+    return c;
+}
+
+// C = A^+ B
+template <typename R> __device__ __forceinline__ M3<R> m_mul_dn(const M3<R>& a, const M3<R>& b)
+{
+    M3<R> c;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) {
+            R xr = R(0), xi = R(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                xr += a.re[k * 3 + r] * b.re[k * 3 + s] + a.im[k * 3 + r] * b.im[k * 3 + s];
+                xi += a.re[k * 3 + r] * b.im[k * 3 + s] - a.im[k * 3 + r] * b.re[k * 3 + s];
+            }
+            c.re[r * 3 + s] = xr;
+            c.im[r * 3 + s] = xi;
+        }
+    return c;
+}
+
+// C = A^+ B^+
+template <typename R> __device__ __forceinline__ M3<R> m_mul_dd(const M3<R>& a, const M3<R>& b)
+{
+    M3<R> c;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) {
+            R xr = R(0), xi = R(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                // conj(a[k][r]) * conj(b[s][k])
+                xr += a.re[k * 3 + r] * b.re[s * 3 + k] - a.im[k * 3 + r] * b.im[s * 3 + k];
+                xi -= a.re[k * 3 + r] * b.im[s * 3 + k] + a.im[k * 3 + r] * b.re[s * 3 + k];
+            }
+            c.re[r * 3 + s] = xr;
+            c.im[r * 3 + s] = xi;
+        }
+    return c;
+}
+
+template <typename R> __device__ __forceinline__ void m_acc(M3<R>& a, const M3<R>& b)
+{
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        a.re[k] += b.re[k];
+        a.im[k] += b.im[k];
+    }
+}
+
+template <typename R> __device__ __forceinline__ M3<R> m_dag(const M3<R>& a)
+{
+    M3<R> c;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) {
+            c.re[r * 3 + s] = a.re[s * 3 + r];
+            c.im[r * 3 + s] = -a.im[s * 3 + r];
+        }
+    return c;
+}
+
+template <typename R> __device__ __forceinline__ R m_retr(const M3<R>& a) { return a.re[0] + a.re[4] + a.re[8]; }
+
+template <typename R, typename S> __device__ __forceinline__ M3<S> m_cast(const M3<R>& a)
+{
+    M3<S> c;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        c.re[k] = (S)a.re[k];
+        c.im[k] = (S)a.im[k];
+    }
+    return c;
+}
+
+// row 2 = complex conjugate of (row 0 x row 1)
+template <typename R> __device__ __forceinline__ void m_complete_row2(M3<R>& a)
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        R xr = a.re[c1] * a.re[3 + c2] - a.im[c1] * a.im[3 + c2] - (a.re[c2] * a.re[3 + c1] - a.im[c2] * a.im[3 + c1]);
+        R xi = a.re[c1] * a.im[3 + c2] + a.im[c1] * a.re[3 + c2] - (a.re[c2] * a.im[3 + c1] + a.im[c2] * a.re[3 + c1]);
+        a.re[6 + c] = xr;
+        a.im[6 + c] = -xi;
+    }
+}
+
+// Gram-Schmidt of rows 0 and 1, then row 2 completes to SU(3).
+template <typename R> __device__ __forceinline__ void m_reunit(M3<R>& a)
+{
+    R n0 = R(0);
+#pragma unroll
+    for (int c = 0; c < 3; c++) n0 += a.re[c] * a.re[c] + a.im[c] * a.im[c];
+    n0 = R(1) / m_sqrt(n0);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        a.re[c] *= n0;
+        a.im[c] *= n0;
+    }
+    R pr = R(0), pi = R(0);  // <row0, row1> = sum conj(r0) r1
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        pr += a.re[c] * a.re[3 + c] + a.im[c] * a.im[3 + c];
+        pi += a.re[c] * a.im[3 + c] - a.im[c] * a.re[3 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        a.re[3 + c] -= pr * a.re[c] - pi * a.im[c];
+        a.im[3 + c] -= pr * a.im[c] + pi * a.re[c];
+    }
+    R n1 = R(0);
+#pragma unroll
+    for (int c = 0; c < 3; c++) n1 += a.re[3 + c] * a.re[3 + c] + a.im[3 + c] * a.im[3 + c];
+    n1 = R(1) / m_sqrt(n1);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        a.re[3 + c] *= n1;
+        a.im[3 + c] *= n1;
+    }
+    m_complete_row2(a);
+}
+
+// ---------------------------------------------------------------------------
+// SU(2) subgroups of SU(3) in quaternion form: q = q0 + i q.sigma is the
+// 2x2 block [[q0 + i q3, q2 + i q1], [-q2 + i q1, q0 - i q3]].
+// ---------------------------------------------------------------------------
+// subgroup s = 0, 1, 2 acts on rows (0,1), (1,2), (0,2), in that order
+__host__ __device__ constexpr int sub_i(int s) { return s == 1 ? 1 : 0; }
+__host__ __device__ constexpr int sub_j(int s) { return s == 0 ? 1 : 2; }
+
+template <typename R> struct Q4 {
+    R q0, q1, q2, q3;
+};
+
+// SU(2) part of the (i,j) block of W: returns k and the unit quaternion v.
+template <typename R> __device__ __forceinline__ R su2_part(const M3<R>& W, int i, int j, Q4<R>& v)
+{
+    const int ii = i * 3 + i, jj = j * 3 + j, ij = i * 3 + j, ji = j * 3 + i;
+    R x0 = (W.re[ii] + W.re[jj]) * R(0.5);
+    R x3 = (W.im[ii] - W.im[jj]) * R(0.5);
+    R x1 = (W.im[ij] + W.im[ji]) * R(0.5);
+    R x2 = (W.re[ij] - W.re[ji]) * R(0.5);
+    R k = m_sqrt(x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
+    R ik = (k > R(0)) ? R(1) / k : R(0);
+    v.q0 = x0 * ik;
+    v.q1 = x1 * ik;
+    v.q2 = x2 * ik;
+    v.q3 = x3 * ik;
+    return k;
+}
+
+// rows i, j of M <- r applied from the left
+template <typename R> __device__ __forceinline__ void left_apply(M3<R>& M, int i, int j, const Q4<R>& r)
+{
+    const R a_re = r.q0, a_im = r.q3;   // r00
+    const R b_re = r.q2, b_im = r.q1;   // r01
+    const R c_re = -r.q2, c_im = r.q1;  // r10
+    const R d_re = r.q0, d_im = -r.q3;  // r11
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        R xr = M.re[i * 3 + c], xi = M.im[i * 3 + c];
+        R yr = M.re[j * 3 + c], yi = M.im[j * 3 + c];
+        M.re[i * 3 + c] = a_re * xr - a_im * xi + b_re * yr - b_im * yi;
+        M.im[i * 3 + c] = a_re * xi + a_im * xr + b_re * yi + b_im * yr;
+        M.re[j * 3 + c] = c_re * xr - c_im * xi + d_re * yr - d_im * yi;
+        M.im[j * 3 + c] = c_re * xi + c_im * xr + d_re * yi + d_im * yr;
+    }
+}
+
+// quaternion product a b
+template <typename R> __device__ __forceinline__ Q4<R> q_mul(const Q4<R>& a, const Q4<R>& b)
+{
+    Q4<R> c;
+    c.q0 = a.q0 * b.q0 - a.q1 * b.q1 - a.q2 * b.q2 - a.q3 * b.q3;
+    // vector part: a0 b + b0 a - a x b
+    c.q1 = a.q0 * b.q1 + b.q0 * a.q1 - (a.q2 * b.q3 - a.q3 * b.q2);
+    c.q2 = a.q0 * b.q2 + b.q0 * a.q2 - (a.q3 * b.q1 - a.q1 * b.q3);
+    c.q3 = a.q0 * b.q3 + b.q0 * a.q3 - (a.q1 * b.q2 - a.q2 * b.q1);
+    return c;
+}
+
+template <typename R> __device__ __forceinline__ Q4<R> q_conj(const Q4<R>& a) { return Q4<R>{ a.q0, -a.q1, -a.q2, -a.q3 }; }
+
+// ---------------------------------------------------------------------------
+// fp64 SU(2) steps as explicit complex 2x2 arithmetic with products
+// (ac - bd, ad + bc) and sums taken in a fixed order: the form the fp64
+// chain is specified in, so that it is reproducible bit for bit.
+// ---------------------------------------------------------------------------
+struct Cx {
+    double re, im;
+};
+__device__ __forceinline__ Cx c_mul(Cx a, Cx b) { return Cx{ a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re }; }
+__device__ __forceinline__ Cx c_add(Cx a, Cx b) { return Cx{ a.re + b.re, a.im + b.im }; }
+__device__ __forceinline__ Cx c_conj(Cx a) { return Cx{ a.re, -a.im }; }
+
+// v = unit SU(2) part of the (i,j) block of W as [[x0+i x3, x2+i x1],
+// [-x2+i x1, x0-i x3]]/k (each component divided by k); returns k.
+__device__ __forceinline__ double su2_part_c(const M3<double>& W, int i, int j, Cx v[2][2])
+{
+    const int ii = i * 3 + i, jj = j * 3 + j, ij = i * 3 + j, ji = j * 3 + i;
+    const double x0 = (W.re[ii] + W.re[jj]) * 0.5;
+    const double x3 = (W.im[ii] - W.im[jj]) * 0.5;
+    const double x1 = (W.im[ij] + W.im[ji]) * 0.5;
+    const double x2 = (W.re[ij] - W.re[ji]) * 0.5;
+    const double k = sqrt(x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
+    if (k == 0.0) return 0.0;
+    v[0][0] = Cx{ x0 / k, x3 / k };
+    v[0][1] = Cx{ x2 / k, x1 / k };
+    v[1][0] = Cx{ -x2 / k, x1 / k };
+    v[1][1] = Cx{ x0 / k, -x3 / k };
+    return k;
+}
+
+// rows i, j of M <- r applied from the left: M_i = r00 M_i + r01 M_j, ...
+__device__ __forceinline__ void left_apply_c(M3<double>& M, int i, int j, const Cx r[2][2])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const Cx a{ M.re[i * 3 + c], M.im[i * 3 + c] };
+        const Cx b{ M.re[j * 3 + c], M.im[j * 3 + c] };
+        const Cx x = c_add(c_mul(r[0][0], a), c_mul(r[0][1], b));
+        const Cx y = c_add(c_mul(r[1][0], a), c_mul(r[1][1], b));
+        M.re[i * 3 + c] = x.re;
+        M.im[i * 3 + c] = x.im;
+        M.re[j * 3 + c] = y.re;
+        M.im[j * 3 + c] = y.im;
+    }
+}
+
+// C = A B for 2x2 complex matrices
+__device__ __forceinline__ void mul2_c(const Cx a[2][2], const Cx b[2][2], Cx c[2][2])
+{
+#pragma unroll
+    for (int p = 0; p < 2; p++)
+#pragma unroll
+        for (int q = 0; q < 2; q++) c[p][q] = c_add(c_mul(a[p][0], b[0][q]), c_mul(a[p][1], b[1][q]));
+}
+
+// ---------------------------------------------------------------------------
+// Link field views.
+// ---------------------------------------------------------------------------
+template <typename R, int NC> struct Links {
+    R* p;
+    size_t cs;  // component stride in elements
+    __device__ __forceinline__ R* slab(int mu, int par) const { return p + (size_t)((mu * 2 + par) * NC) * cs; }
+};
+
+template <typename R, int NC> __device__ __forceinline__ M3<R> load_link(const R* __restrict__ s, size_t cs, int cb)
+{
+    M3<R> m;
+#pragma unroll
+    for (int k = 0; k < (NC == 18 ? 9 : 6); k++) {
+        m.re[k] = s[(size_t)(2 * k) * cs + cb];
+        m.im[k] = s[(size_t)(2 * k + 1) * cs + cb];
+    }
+    if (NC == 12) m_complete_row2(m);
+    return m;
+}
+
+template <typename R, int NC> __device__ __forceinline__ void store_link(R* __restrict__ s, size_t cs, int cb, const M3<R>& m)
+{
+#pragma unroll
+    for (int k = 0; k < (NC == 18 ? 9 : 6); k++) {
+        s[(size_t)(2 * k) * cs + cb] = m.re[k];
+        s[(size_t)(2 * k + 1) * cs + cb] = m.im[k];
+    }
+}
+
+// Convenience: load U_mu at site coordinates n (any parity).
+template <typename R, int NC> __device__ __forceinline__ M3<R> load_at(const Links<R, NC>& U, const Geo& g, int mu, const int n[4])
+{
+    int i = lex_index(g, n);
+    int par = (n[0] + n[1] + n[2] + n[3]) & 1;
+    return load_link<R, NC>(U.slab(mu, par), U.cs, i >> 1);
+}
+
+// Staple sum A_mu(n): for nu != mu ascending, the forward term
+// U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+ then the backward term
+// U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu); Re Tr(U_mu(n) A) is the sum of the
+// six plaquettes containing U_mu(n).  Computed in precision C from links of
+// precision R.
+template <typename R, int NC, typename C>
+__device__ __forceinline__ M3<C> staple_sum(const Links<R, NC>& U, const Geo& g, int mu, const int n[4])
+{
+    M3<C> A;
+    m_set_zero(A);
+    int npm[4] = { n[0], n[1], n[2], n[3] };
+    npm[mu] = wrap_add(n[mu], 1, g.L[mu]);
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        int npn[4] = { n[0], n[1], n[2], n[3] };
+        npn[nu] = wrap_add(n[nu], 1, g.L[nu]);
+        int nmn[4] = { n[0], n[1], n[2], n[3] };
+        nmn[nu] = wrap_add(n[nu], -1, g.L[nu]);
+        int npm_mn[4] = { npm[0], npm[1], npm[2], npm[3] };
+        npm_mn[nu] = nmn[nu];
+        {
+            M3<C> a = m_cast<R, C>(load_at(U, g, nu, npm));
+            M3<C> b = m_cast<R, C>(load_at(U, g, mu, npn));
+            M3<C> c = m_cast<R, C>(load_at(U, g, nu, n));
+            m_acc(A, m_mul_nd(m_mul_nd(a, b), c));
+        }
+        {
+            M3<C> a = m_cast<R, C>(load_at(U, g, nu, npm_mn));
+            M3<C> b = m_cast<R, C>(load_at(U, g, mu, nmn));
+            M3<C> c = m_cast<R, C>(load_at(U, g, nu, nmn));
+            m_acc(A, m_mul(m_mul_dd(a, b), c));
+        }
+    }
+    return A;
+}
+
+// Logical block id with XCD-aware remapping: the hardware deals workgroups
+// round-robin over the 8 XCDs, so logical blocks are renumbered to give each
+// XCD one contiguous range of sites (neighbouring sites then share an L2).
+__device__ __forceinline__ int logical_block(int b, int nblocks, int remap)
+{
+    if (!remap) return b;
+    const int x = b & 7, y = b >> 3;
+    const int q = nblocks >> 3, r = nblocks & 7;
+    return (x < r) ? x * (q + 1) + y : r * (q + 1) + (x - r) * q + y;
+}
+
+// Exponential of an anti-hermitian traceless 3x3 matrix X: Taylor series of
+// X / 2^s (Horner, order N) followed by s squarings, with s chosen so that
+// the Frobenius norm of X / 2^s is at most 1/4.
+template <typename R, int N> __device__ __forceinline__ M3<R> m_exp_ah(const M3<R>& X)
+{
+    R nrm = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; k++) nrm += X.re[k] * X.re[k] + X.im[k] * X.im[k];
+    nrm = m_sqrt(nrm);
+    int s = 0;
+    R sc = R(1);
+    while (nrm * sc > R(0.25) && s < 40) {
+        sc *= R(0.5);
+        s++;
+    }
+    M3<R> Y;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        Y.re[k] = X.re[k] * sc;
+        Y.im[k] = X.im[k] * sc;
+    }
+    // Horner: E = 1 + Y (1 + Y/2 (1 + Y/3 (... (1 + Y/N))))
+    M3<R> E;
+    m_set_one(E);
+#pragma unroll
+    for (int k = N; k >= 1; k--) {
+        M3<R> T = m_mul(Y, E);
+        const R f = R(1) / R(k);
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            E.re[q] = T.re[q] * f;
+            E.im[q] = T.im[q] * f;
+        }
+        E.re[0] += R(1);
+        E.re[4] += R(1);
+        E.re[8] += R(1);
+    }
+    for (int q = 0; q < s; q++) E = m_mul(E, E);
+    return E;
+}
+
+}  // namespace msmc

@@ -1,0 +1,104 @@
+// k_flow.hip -- one stage of the third-order Runge-Kutta Wilson flow
+// (Sec. IV.B) in 2N-storage form.
+//
+// Z(W) = -(1/2)(Om - Om^+) + (1/6) Tr(Om - Om^+), Om = W A (A the staple
+// sum); the three stages are W1 = exp(Z0/4) W0, W2 = exp(8/9 Z1 - 17/36 Z0) W1,
+// W3 = exp(3/4 Z2 - 8/9 Z1 + 17/36 Z0) W2 with Z_i = eps Z(W_i).  With the
+// running generator X (8 reals per link): X <- cz * eps * Z + ca * X using
+// (cz, ca) = (1/4, 0), (8/9, -17/9), (3/4, -1), then W <- exp(X) W.
+// X is anti-hermitian traceless, stored as (Im X00, Im X11, Re X01, Im X01,
+// Re X02, Im X02, Re X12, Im X12).
+#include "kernels.hpp"
+
+namespace msmc {
+
+__device__ __forceinline__ int find_lattice_f(const int* __restrict__ bbeg, int nlat, int lb)
+{
+    int lo = 0, hi = nlat - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (bbeg[mid] <= lb)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename R> struct FlowExpOrder;
+template <> struct FlowExpOrder<double> { static constexpr int N = 12; };
+template <> struct FlowExpOrder<float> { static constexpr int N = 8; };
+
+template <typename R, int NC>
+__global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double cz, double ca, int first)
+{
+    const int lb = logical_block(blockIdx.x, gr.nblocks, gr.remap);
+    const int l = find_lattice_f(gr.bbeg, gr.nlat, lb);
+    const LatDesc& d = gr.descs[l];
+    const int Vh = d.g.Vh;
+    const int e = (lb - gr.bbeg[l]) * (int)blockDim.x + (int)threadIdx.x;
+    if (e >= 8 * Vh) return;
+    const int slab = e / Vh, cb = e - slab * Vh, mu = slab >> 1, par = slab & 1;
+    const Links<R, NC> W{ (R*)d.U, d.cs };
+    int n[4];
+    cb_coords(d.g, cb, par, n);
+    const M3<R> A = staple_sum<R, NC, R>(W, d.g, mu, n);
+    const M3<R> w = load_link<R, NC>(W.slab(mu, par), W.cs, cb);
+    const M3<R> Om = m_mul(w, A);
+    // Z in 8-real form
+    const R tr3 = (Om.im[0] + Om.im[4] + Om.im[8]) / R(3);
+    R z[8];
+    z[0] = -Om.im[0] + tr3;
+    z[1] = -Om.im[4] + tr3;
+    z[2] = R(-0.5) * (Om.re[1] - Om.re[3]);
+    z[3] = R(-0.5) * (Om.im[1] + Om.im[3]);
+    z[4] = R(-0.5) * (Om.re[2] - Om.re[6]);
+    z[5] = R(-0.5) * (Om.im[2] + Om.im[6]);
+    z[6] = R(-0.5) * (Om.re[5] - Om.re[7]);
+    z[7] = R(-0.5) * (Om.im[5] + Om.im[7]);
+    R* xp = (R*)d.aux + (size_t)(slab * 8) * d.cs8 + cb;
+    R x[8];
+    const R fz = (R)(cz * eps), fa = (R)ca;
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+        x[a] = fz * z[a];
+        if (!first) x[a] += fa * xp[(size_t)a * d.cs8];
+        xp[(size_t)a * d.cs8] = x[a];
+    }
+    M3<R> X;
+    X.re[0] = R(0);
+    X.im[0] = x[0];
+    X.re[4] = R(0);
+    X.im[4] = x[1];
+    X.re[8] = R(0);
+    X.im[8] = -(x[0] + x[1]);
+    X.re[1] = x[2];
+    X.im[1] = x[3];
+    X.re[3] = -x[2];
+    X.im[3] = x[3];
+    X.re[2] = x[4];
+    X.im[2] = x[5];
+    X.re[6] = -x[4];
+    X.im[6] = x[5];
+    X.re[5] = x[6];
+    X.im[5] = x[7];
+    X.re[7] = -x[6];
+    X.im[7] = x[7];
+    const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N>(X);
+    const Links<R, NC> D{ (R*)d.aux2, d.cs };
+    store_link<R, NC>(D.slab(mu, par), D.cs, cb, m_mul(E, w));
+}
+
+hipError_t launch_flow_stage(int prec, const Grid& gr, double eps, double cz, double ca, int first, hipStream_t st)
+{
+    if (gr.nblocks <= 0) return hipSuccess;
+    switch (prec) {
+    case PREC_F64: k_flow_stage<double, 18><<<gr.nblocks, gr.block, 0, st>>>(gr, eps, cz, ca, first); break;
+    case PREC_F32: k_flow_stage<float, 18><<<gr.nblocks, gr.block, 0, st>>>(gr, eps, cz, ca, first); break;
+    case PREC_F32_R12: k_flow_stage<float, 12><<<gr.nblocks, gr.block, 0, st>>>(gr, eps, cz, ca, first); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace msmc

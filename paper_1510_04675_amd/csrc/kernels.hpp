@@ -1,0 +1,110 @@
+// kernels.hpp -- host-visible launch interface of the HIP kernels.  The
+// C-ABI layer (capi.cpp) builds descriptor tables and calls these launchers;
+// each launcher dispatches on the storage precision to a kernel template.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace msmc {
+
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_F32_R12 = 2 };
+
+inline int prec_ncomp(int p) { return p == PREC_F32_R12 ? 12 : 18; }
+inline size_t prec_real_bytes(int p) { return p == PREC_F64 ? 8 : 4; }
+
+// Per-lattice descriptor read by the batched kernels.
+struct LatDesc {
+    void* U;       // link field
+    void* aux;     // second buffer (momenta, flow generator, ping-pong links)
+    void* aux2;
+    size_t cs;     // component stride of U (elements)
+    size_t cs8;    // component stride of the 8-real aux fields (elements)
+    Geo g;
+    double beta;
+    uint32_t seed, lid;
+};
+
+// Block partition: lattice l owns logical blocks [bbeg[l], bbeg[l+1]).
+// All launchers take (descs, bbeg, nlat, nblocks) and a block size.
+struct Grid {
+    const LatDesc* descs;
+    const int* bbeg;
+    int nlat;
+    int nblocks;
+    int block;
+    int remap;
+};
+
+struct HbArgs {
+    int n_hits;
+    int max_tries;
+    int sampler;  // 0 = Kennedy-Pendleton, 1 = Creutz
+};
+
+// --- update kernels (k_update.hip) -----------------------------------------
+// One checkerboard phase (mu, parity) of the heat bath (kind 0) or the
+// overrelaxation (kind 1).  Work unit: one link of that direction and parity
+// per thread, bbeg counts ceil(Vh / block) blocks per lattice.
+hipError_t launch_phase(int prec, int kind, const Grid& gr, int mu, int par, const uint64_t* sweep_base,
+                        int sweep_off, HbArgs hb, unsigned long long* exhausted, hipStream_t st);
+hipError_t launch_phase_f64(int kind, const Grid& gr, int mu, int par, const uint64_t* sweep_base, int sweep_off,
+                            HbArgs hb, unsigned long long* exhausted, hipStream_t st);
+hipError_t launch_phase_f32(int prec, int kind, const Grid& gr, int mu, int par, const uint64_t* sweep_base,
+                            int sweep_off, HbArgs hb, unsigned long long* exhausted, hipStream_t st);
+
+// Per-link kernels: bbeg counts ceil(8*Vh / 256) blocks per lattice.
+hipError_t launch_init(int prec, int hot, const Grid& gr, hipStream_t st);
+hipError_t launch_reunit(int prec, const Grid& gr, const uint64_t* sweep_base, int sweep_off, int every,
+                         hipStream_t st);
+hipError_t launch_gauge(int prec, const Grid& gr, uint32_t seed, hipStream_t st);
+// host exchange layout <-> structure of arrays (one lattice, staging in fp64)
+hipError_t launch_to_aos(int prec, const LatDesc* d, const Geo& g, const void* U, size_t cs, double* aos,
+                         hipStream_t st);
+hipError_t launch_from_aos(int prec, const Geo& g, void* U, size_t cs, const double* aos, hipStream_t st);
+// copy with precision conversion between two fields of the same shape
+hipError_t launch_convert(int pdst, void* dst, size_t cs_dst, int psrc, const void* src, size_t cs_src, int Vh,
+                          hipStream_t st);
+// largest deviation from SU(3) per block (max of |UU^+ - 1| and |det U - 1|)
+hipError_t launch_check(int prec, const Geo& g, const void* U, size_t cs, double* block_max, int* block_arg,
+                        int nblk, hipStream_t st);
+
+// --- reductions (k_measure.hip) --------------------------------------------
+// Sum over sites and planes of 1 - (1/3) Re Tr U_munu(n) in fp64.  Work unit:
+// one site per thread, bbeg counts ceil(V / 256) blocks per lattice.
+hipError_t launch_plaq_partial(int prec, const Grid& gr, double* partials, hipStream_t st);
+// out[l * stride + off] = sum of partials of lattice l (fixed order).
+hipError_t launch_reduce_final(const Grid& gr, const double* partials, double* out, int stride, int off,
+                               hipStream_t st);
+// Clover topological charge density summed per block (fp64).
+hipError_t launch_qtop_partial(int prec, const Grid& gr, double* partials, hipStream_t st);
+// Clover energy density summed per block (fp64).
+hipError_t launch_energy_partial(int prec, const Grid& gr, double* partials, hipStream_t st);
+
+// --- HMC (k_hmc.hip) ---------------------------------------------------------
+// aux = momenta (8 reals per link, stride cs8), aux2 = destination links.
+// Per-link work unit over all 4V links: bbeg counts ceil(8*Vh / block).
+hipError_t launch_mom_refresh(int prec, const Grid& gr, uint64_t traj, hipStream_t st);
+hipError_t launch_kick_drift(int prec, const Grid& gr, double eps_kick, double eps_drift, int drift,
+                             hipStream_t st);
+hipError_t launch_kinetic_partial(int prec, const Grid& gr, double* partials, hipStream_t st);
+
+// --- Wilson flow (k_flow.hip) ------------------------------------------------
+// aux = 2N-storage generator (8 reals per link), aux2 = destination links.
+hipError_t launch_flow_stage(int prec, const Grid& gr, double eps, double cz, double ca, int first,
+                             hipStream_t st);
+
+// --- restriction / prolongation (k_prolong.hip), fp64 fine field ------------
+hipError_t launch_restrict(int pf, const Geo& gf, const void* Uf, size_t csf, int pc, const Geo& gc, void* Uc,
+                           size_t csc, hipStream_t st);
+hipError_t launch_transfer(int pc, const Geo& gc, const void* Uc, size_t csc, const Geo& gf, double* Uf,
+                           size_t csf, hipStream_t st);
+hipError_t launch_ape(const Geo& gf, const double* Uold, double* Unew, size_t csf, int d, double c,
+                      hipStream_t st);
+hipError_t launch_partial_action(const Geo& gf, const double* U, size_t csf, int d, double* block_sums, int nblk,
+                                 hipStream_t st);
+
+}  // namespace msmc

@@ -1,0 +1,171 @@
+// phase.hpp -- one checkerboard phase of the Cabibbo-Marinari heat bath or of
+// overrelaxation (Sec. IV.A); included by k_phase_f64.hip (fp64, compiled
+// without floating-point contraction) and k_phase_f32.hip (fp32).
+//
+// For the link U_mu(n) the local weight is exp((beta/3) Re Tr(U A)), A the
+// staple sum.  With W = U A, each SU(2) subgroup (0,1), (1,2), (0,2) in turn
+// is updated by U <- R U (and W <- R W): R's 2x2 block is r = g v^+, v the
+// unit SU(2) part k v of W's block, g drawn with density exp(alpha g0) on the
+// SU(2) Haar measure, alpha = 2 beta k / 3 (Kennedy-Pendleton: delta = 1 - g0
+// proposed from Gamma(3/2) with rate alpha and accepted with probability
+// sqrt(1 - delta/2); Creutz: g0 from exp(alpha g0) on [-1, 1] by inversion,
+// accepted with probability sqrt(1 - g0^2)); the direction of g is uniform on
+// the sphere.  A draw whose trials all fail leaves the subgroup unchanged.
+// Overrelaxation uses r = (v^+)^2, which keeps Re Tr(U A) and the action.
+//
+// One thread per link of direction mu and the given parity; no two links of
+// one phase share a plaquette, so the phase is a single data-parallel launch.
+#pragma once
+
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace msmc {
+
+__device__ __forceinline__ int find_lattice_p(const int* __restrict__ bbeg, int nlat, int lb)
+{
+    int lo = 0, hi = nlat - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (bbeg[mid] <= lb)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Draw g0 (trial t uses Philox word (P_HB, mu, sub, hit, t)); false if all
+// max_tries trials were rejected.
+template <typename R>
+__device__ __forceinline__ bool draw_g0(const Rng& rng, R alpha, int mu, int sg, int h, const HbArgs& hb, R& g0)
+{
+    for (int t = 0; t < hb.max_tries; t++) {
+        const uint4 w = rng.draw(ctr_word(P_HB, mu, sg, h, t));
+        const R u0 = u01<R>(w.x), u1 = u01<R>(w.y), u2 = u01<R>(w.z), u3 = u01<R>(w.w);
+        if (hb.sampler == 0) {
+            R cs, sn;
+            m_cossin2pi(u1, &cs, &sn);
+            const R delta = -(m_log(u0) + cs * cs * m_log(u2)) / alpha;
+            if (u3 * u3 <= R(1) - R(0.5) * delta) {
+                g0 = R(1) - delta;
+                return true;
+            }
+        } else {
+            const R e = m_exp(R(-2) * alpha);
+            const R x = R(1) + m_log(e + u0 * (R(1) - e)) / alpha;
+            if (u1 * u1 <= R(1) - x * x) {
+                g0 = x;
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
+// Direction of g: cos(theta) = 2 u0 - 1, phi = 2 pi u1 (Philox word
+// (P_HB_DIR, mu, sub, hit, 0)); g = (g0, s sin(theta) cos(phi),
+// s sin(theta) sin(phi), s cos(theta)), s = sqrt(1 - g0^2).
+template <typename R>
+__device__ __forceinline__ void draw_dir(const Rng& rng, int mu, int sg, int h, R g0, R g[4])
+{
+    const uint4 w = rng.draw(ctr_word(P_HB_DIR, mu, sg, h, 0));
+    const R ct = R(2) * u01<R>(w.x) - R(1);
+    const R stt = m_sqrt(m_max(R(0), R(1) - ct * ct));
+    R cp, sp;
+    m_cossin2pi(u01<R>(w.y), &cp, &sp);
+    const R sr = m_sqrt(m_max(R(0), R(1) - g0 * g0));
+    g[0] = g0;
+    g[1] = sr * stt * cp;
+    g[2] = sr * stt * sp;
+    g[3] = sr * ct;
+}
+
+template <typename R, int NC, int KIND>
+__global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const uint64_t* __restrict__ sweep_base,
+                                               int sweep_off, HbArgs hb, unsigned long long* exhausted)
+{
+    constexpr bool kF64 = std::is_same<R, double>::value;
+    const int lb = logical_block(blockIdx.x, gr.nblocks, gr.remap);
+    const int l = find_lattice_p(gr.bbeg, gr.nlat, lb);
+    const LatDesc& d = gr.descs[l];
+    const Geo g = d.g;
+    const int cb = (lb - gr.bbeg[l]) * (int)blockDim.x + (int)threadIdx.x;
+    if (cb >= g.Vh) return;
+
+    const Links<R, NC> U{ (R*)d.U, d.cs };
+    int n[4];
+    cb_coords(g, cb, par, n);
+    const M3<R> A = staple_sum<R, NC, R>(U, g, mu, n);
+    R* s = U.slab(mu, par);
+    M3<R> u = load_link<R, NC>(s, U.cs, cb);
+    M3<R> W = m_mul(u, A);
+
+    Rng rng{ d.seed, d.lid, (uint32_t)lex_index(g, n), 0 };
+    if (KIND == 0) rng.step = *sweep_base + (uint64_t)sweep_off;
+    const R beta = (R)d.beta;
+    const int nh = (KIND == 0) ? hb.n_hits : 1;
+
+    for (int h = 0; h < nh; h++) {
+#pragma unroll
+        for (int sg = 0; sg < 3; sg++) {
+            const int i = sub_i(sg), j = sub_j(sg);
+            if constexpr (kF64) {
+                Cx v[2][2];
+                const double k = su2_part_c(W, i, j, v);
+                if (k == 0.0) continue;
+                const Cx vd[2][2] = { { c_conj(v[0][0]), c_conj(v[1][0]) }, { c_conj(v[0][1]), c_conj(v[1][1]) } };
+                Cx r[2][2];
+                if (KIND == 0) {
+                    const double alpha = 2.0 * beta * k / 3.0;
+                    double g0;
+                    if (!draw_g0<double>(rng, alpha, mu, sg, h, hb, g0)) {
+                        if (exhausted) atomicAdd(exhausted, 1ull);
+                        continue;
+                    }
+                    double q[4];
+                    draw_dir<double>(rng, mu, sg, h, g0, q);
+                    const Cx gm[2][2] = { { Cx{ q[0], q[3] }, Cx{ q[2], q[1] } }, { Cx{ -q[2], q[1] }, Cx{ q[0], -q[3] } } };
+                    mul2_c(gm, vd, r);
+                } else {
+                    mul2_c(vd, vd, r);
+                }
+                left_apply_c(u, i, j, r);
+                left_apply_c(W, i, j, r);
+            } else {
+                Q4<R> v;
+                const R k = su2_part(W, i, j, v);
+                if (!(k > R(0))) continue;
+                Q4<R> r;
+                if (KIND == 0) {
+                    const R alpha = R(2) * beta * k / R(3);
+                    R g0;
+                    if (!draw_g0<R>(rng, alpha, mu, sg, h, hb, g0)) {
+                        if (exhausted) atomicAdd(exhausted, 1ull);
+                        continue;
+                    }
+                    R q[4];
+                    draw_dir<R>(rng, mu, sg, h, g0, q);
+                    r = q_mul(Q4<R>{ q[0], q[1], q[2], q[3] }, q_conj(v));
+                } else {
+                    const Q4<R> vd = q_conj(v);
+                    r = q_mul(vd, vd);
+                }
+                left_apply(u, i, j, r);
+                left_apply(W, i, j, r);
+            }
+        }
+    }
+    store_link<R, NC>(s, U.cs, cb, u);
+}
+
+template <typename R, int NC, int KIND>
+static hipError_t launch_phase_t(const Grid& gr, int mu, int par, const uint64_t* sb, int so, HbArgs hb,
+                                 unsigned long long* ex, hipStream_t st)
+{
+    k_phase<R, NC, KIND><<<gr.nblocks, gr.block, 0, st>>>(gr, mu, par, sb, so, hb, ex);
+    return hipGetLastError();
+}
+
+}  // namespace msmc

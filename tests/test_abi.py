@@ -1,0 +1,55 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the
+header declares, and validates arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msmc.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(su3_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1510_04675_amd import capi
+    L = capi.lib()
+    names = _declared()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(capi.SIGNATURES), set(names) ^ set(capi.SIGNATURES)
+
+
+def test_field_bytes_and_shape_validation():
+    from paper_1510_04675_amd import capi
+    # 18 reals per link record, component stride padded to an odd number of 128 B lines
+    b64 = capi.su3_field_bytes([4, 4, 4, 4], capi.SU3_FP64)
+    assert b64 >= 1024 * 144 and b64 % 128 == 0
+    b32 = capi.su3_field_bytes([32, 32, 32, 32], capi.SU3_FP32)
+    r12 = capi.su3_field_bytes([32, 32, 32, 32], capi.SU3_FP32_R12)
+    assert b32 >= 4 * 32**4 * 72 and r12 >= 4 * 32**4 * 48 and r12 < b32
+    for bad in ([3, 4, 4, 4], [4, 4, 0, 4], [4, 4, 4, 1], [1024, 1024, 1024, 2]):
+        with pytest.raises(capi.SU3Error) as e:
+            capi.su3_field_bytes(bad, capi.SU3_FP64)
+        assert e.value.code == 2
+    with pytest.raises(capi.SU3Error) as e:
+        capi.su3_field_bytes([4, 4, 4, 4], 7)
+    assert e.value.code == 1
+
+
+def test_null_handles_are_rejected():
+    from paper_1510_04675_amd import capi
+    L = capi.lib()
+    assert L.su3_init_cold(None) == 1
+    assert L.su3_plaquette(None, None) == 1
+    assert "NULL" in capi.su3_last_error()
+    assert L.su3_field_destroy(None) == 0
+    assert L.su3_set_launch(100, 1) == 1
+    assert L.su3_profile_read(3, None, None) == 1
+    assert L.su3_batch_sweep_hb_or(None, 0, None, None, None, 0, 1, None, None) == 1

@@ -1,0 +1,318 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle on
+the same seeded inputs.  FP64 paths must agree per real component to 1e-12
+(links) and 1e-13 (plaquettes); FP32 paths within the tolerances derived in
+the design notes (storage rounding 6e-8 per component, amplified by the few
+hundred operations of a sweep)."""
+import os
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1510_04675_amd as msmc
+    msmc.lib()
+    return msmc
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _threads(orc):
+    orc.set_threads(min(16, os.cpu_count() or 1))
+
+
+def field(m, dims, prec="fp64"):
+    return m.Field(dims, prec)
+
+
+def P(n_or=4, hits=1, tries=64, reunit=0, sampler=0):
+    import paper_1510_04675_amd as msmc
+    return msmc.hb_params(n_or, hits, tries, reunit, sampler)
+
+
+def test_hot_start_matches_oracle(m, orc):
+    for d in ([4, 4, 4, 4], [6, 2, 4, 8]):
+        f = field(m, d)
+        m.su3_init_hot(f, 1, 3)
+        U = m.su3_field_to_host(f)
+        ref = orc.init_hot(d, 1, 3)
+        assert np.max(np.abs(U - ref)) < 1e-14
+
+
+def test_host_roundtrip_and_precisions(m, orc):
+    d = [4, 6, 2, 4]
+    U = si.random_field(d, 5)
+    f = field(m, d)
+    m.su3_field_from_host(f, U)
+    assert np.array_equal(m.su3_field_to_host(f), U)
+    g = field(m, d, "fp32")
+    m.su3_field_from_host(g, U)
+    assert np.array_equal(m.su3_field_to_host(g), U.astype(np.float32).astype(np.float64))
+    r = field(m, d, "fp32_r12")
+    m.su3_field_from_host(r, U)
+    assert np.max(np.abs(m.su3_field_to_host(r) - U)) < 1e-6
+    h = field(m, d)
+    m.su3_field_copy(h, g)
+    assert np.array_equal(m.su3_field_to_host(h), m.su3_field_to_host(g))
+
+
+def test_plaquette_action_charge_energy_match_oracle(m, orc):
+    d = [6, 4, 4, 6]
+    U = si.random_field(d, 7)
+    orc.wilson_flow(d, U, 0.05, 3)  # smoother field so Q is not pure noise
+    f = field(m, d)
+    m.su3_field_from_host(f, U)
+    assert abs(m.su3_plaquette(f) - orc.plaquette(d, U)) < 1e-13
+    assert abs(m.su3_action(f, 5.7) - orc.action(d, U, 5.7)) < 1e-9
+    assert abs(m.su3_topological_charge(f) - orc.topological_charge(d, U)) < 1e-11
+    assert abs(m.su3_clover_energy(f) - orc.clover_energy(d, U)) < 1e-12
+
+
+def test_gauge_transform_matches_oracle(m, orc):
+    d = [4, 4, 2, 4]
+    U = si.random_field(d, 8)
+    f = field(m, d)
+    m.su3_field_from_host(f, U)
+    m.su3_gauge_transform(f, 44)
+    orc.gauge_transform(d, U, 44)
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-13
+
+
+def test_config1_fp64_ten_sweeps_per_link(m, orc):
+    """4^4, beta = 6, FP64, hot start (seed 1), 10 sweeps of 1 HB + 4 OR:
+    every real component of the final 1024 links within 1e-12 and all ten
+    plaquettes within 1e-13 of the oracle."""
+    d = [4, 4, 4, 4]
+    f = field(m, d)
+    m.su3_init_hot(f, 1, 0)
+    h = m.su3_sweep_hb_or(f, 6.0, 1, 0, 0, 10, P())
+    U = orc.init_hot(d, 1, 0)
+    href, ex = orc.sweep_hb_or(d, U, 6.0, 1, 0, 0, 10)
+    assert ex == 0 and m.su3_last_exhausted(f) == 0
+    assert np.max(np.abs(h - href)) < 1e-13
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
+
+
+def test_fp64_ragged_lattice_several_blocks(m, orc):
+    """12x10x6x8: 2880 links per phase = 11.25 blocks of 256 (ragged tail),
+    non-power-of-two extents, reunitarization every 2 sweeps, first_sweep 7."""
+    d = [12, 10, 6, 8]
+    f = field(m, d)
+    m.su3_init_hot(f, 9, 2)
+    h = m.su3_sweep_hb_or(f, 5.8, 9, 2, 7, 3, P(n_or=2, reunit=2))
+    U = orc.init_hot(d, 9, 2)
+    href, _ = orc.sweep_hb_or(d, U, 5.8, 9, 2, 7, 3, n_or=2, reunit_every=2)
+    assert np.max(np.abs(h - href)) < 1e-13
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
+
+
+@pytest.mark.parametrize("sampler,hits,tries", [(1, 1, 64), (0, 3, 64), (0, 1, 1), (1, 2, 1)])
+def test_sampler_hits_and_exhaustion_match_oracle(m, orc, sampler, hits, tries):
+    d = [4, 2, 4, 2]
+    f = field(m, d)
+    m.su3_init_hot(f, 4, 0)
+    beta = 1.0 if tries == 1 else 6.0
+    h = m.su3_sweep_hb_or(f, beta, 4, 0, 0, 3, P(n_or=1, hits=hits, tries=tries, sampler=sampler))
+    U = orc.init_hot(d, 4, 0)
+    href, ex = orc.sweep_hb_or(d, U, beta, 4, 0, 0, 3, n_or=1, n_hb_hits=hits, hb_max_tries=tries, sampler=sampler)
+    assert m.su3_last_exhausted(f) == ex
+    if tries == 1:
+        assert ex > 0
+    assert np.max(np.abs(h - href)) < 1e-13
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
+
+
+def fp32_link_stats(Ugpu, Uref):
+    """Per-link largest component deviation: median, 99.9th percentile, max."""
+    dev = np.max(np.abs(Ugpu - Uref), axis=(2, 3, 4)).ravel()
+    return float(np.median(dev)), float(np.quantile(dev, 0.999)), float(dev.max()), dev
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_r12"])
+def test_fp32_sweeps_track_fp64_oracle(m, orc, prec):
+    """FP32 storage and arithmetic from the FP32-rounded copy of an
+    oracle-thermalized field, one sweep of 1 HB + 1 OR (overrelaxation
+    amplifies a perturbation about 5x per pass, so longer FP32 chains
+    separate from the FP64 one by chaos, not by error).  Bars: plaquette
+    within 1e-6 of the FP64 oracle; per-link deviation median below 1e-5 and
+    99.9th percentile below 1e-3 (FP32 rounding 6e-8 amplified by the sweep;
+    a flipped FP32 sampler decision would give an O(1) outlier, allowed for
+    at most 1 link in 10^4)."""
+    d = [8, 4, 4, 8]
+    U = orc.init_hot(d, 2, 0)
+    orc.sweep_hb_or(d, U, 6.0, 2, 0, 0, 8)
+    f = field(m, d, prec)
+    m.su3_field_from_host(f, U)
+    h = m.su3_sweep_hb_or(f, 6.0, 2, 0, 100, 1, P(n_or=1, reunit=1))
+    href, _ = orc.sweep_hb_or(d, U, 6.0, 2, 0, 100, 1, n_or=1, reunit_every=1)
+    med, q999, mx, dev = fp32_link_stats(m.su3_field_to_host(f), U)
+    print(f"{prec}: plaquette diff {abs(h[0] - href[0]):.2e}, link dev median {med:.2e} q99.9 {q999:.2e} max {mx:.2e}")
+    assert abs(h[0] - href[0]) < 1e-6
+    assert med < 1e-5 and q999 < 1e-3
+    assert np.count_nonzero(dev > 1e-2) <= dev.size // 10000
+
+
+def test_launch_shape_and_resume_invariance(m, orc):
+    """Bitwise identical results for every phase-kernel launch shape, and N
+    sweeps equal N/2 + N/2 sweeps."""
+    d = [8, 6, 4, 4]
+    ref = None
+    try:
+        for block, remap in ((64, 0), (128, 1), (256, 1), (512, 0), (512, 1)):
+            m.su3_set_launch(block, remap)
+            f = field(m, d, "fp32")
+            m.su3_init_hot(f, 6, 1)
+            m.su3_sweep_hb_or(f, 6.0, 6, 1, 0, 2, P(n_or=2))
+            m.su3_sweep_hb_or(f, 6.0, 6, 1, 2, 2, P(n_or=2))
+            U = m.su3_field_to_host(f)
+            if ref is None:
+                ref = U
+            assert np.array_equal(U, ref), (block, remap)
+    finally:
+        m.su3_set_launch(0, 1)
+    f = field(m, d, "fp32")
+    m.su3_init_hot(f, 6, 1)
+    m.su3_sweep_hb_or(f, 6.0, 6, 1, 0, 4, P(n_or=2))
+    assert np.array_equal(m.su3_field_to_host(f), ref)
+
+
+def test_batch_equals_separate_calls(m, orc):
+    """One batched graph launch over lattices of uneven shapes gives bitwise
+    the fields and plaquettes of separate calls; replaying the cached graph
+    continues the chain."""
+    shapes = [[4, 4, 4, 4], [6, 4, 2, 4], [8, 2, 4, 6]]
+    betas = [5.9, 6.05, 6.2]
+    for prec in ("fp64", "fp32_r12"):
+        fs = [field(m, d, prec) for d in shapes]
+        gs = [field(m, d, prec) for d in shapes]
+        for i, (a, b) in enumerate(zip(fs, gs)):
+            m.su3_init_hot(a, 10 + i, i)
+            m.su3_init_hot(b, 10 + i, i)
+        for rep in range(2):
+            pb = m.su3_batch_sweep_hb_or(fs, betas, [10, 11, 12], [0, 1, 2], 3 * rep, 3, P(n_or=2, reunit=2))
+            for i, g in enumerate(gs):
+                h = m.su3_sweep_hb_or(g, betas[i], 10 + i, i, 3 * rep, 3, P(n_or=2, reunit=2))
+                assert np.array_equal(h, pb[:, i])
+        for a, b in zip(fs, gs):
+            assert np.array_equal(m.su3_field_to_host(a), m.su3_field_to_host(b))
+    # and the FP64 member matches the oracle
+    d = shapes[1]
+    U = orc.init_hot(d, 11, 1)
+    orc.sweep_hb_or(d, U, 6.05, 11, 1, 0, 6, n_or=2, reunit_every=2)
+    f = field(m, d)
+    m.su3_init_hot(f, 11, 1)
+    m.su3_batch_sweep_hb_or([f], [6.05], [11], [1], 0, 6, P(n_or=2, reunit=2))
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
+
+
+def test_hmc_trajectory_matches_oracle(m, orc):
+    """FP64 HMC: momenta, leapfrog, dH and the Metropolis decision."""
+    d = [4, 4, 4, 4]
+    U = orc.init_hot(d, 5, 0)
+    orc.sweep_hb_or(d, U, 6.0, 5, 0, 0, 5)
+    f = field(m, d)
+    m.su3_field_from_host(f, U)
+    for traj in range(3):
+        acc, dH = m.su3_hmc_trajectory(f, 6.0, 1.0, 12, 5, 0, traj, 1)
+        racc, rdH = orc.hmc_trajectory(d, U, 6.0, 1.0, 12, 5, 0, traj, 1)
+        assert acc == racc
+        assert abs(dH - rdH) < 1e-8 * max(1.0, abs(rdH)), (dH, rdH)
+        assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-11
+    # a rejected trajectory leaves the field unchanged bit for bit
+    before = m.su3_field_to_host(f)
+    acc, dH = m.su3_hmc_trajectory(f, 6.0, 4.0, 2, 5, 0, 99, 1)
+    assert not acc and dH > 20
+    assert np.array_equal(m.su3_field_to_host(f), before)
+
+
+def test_hmc_fp32_dh_tracks_fp64(m, orc):
+    d = [8, 8, 4, 4]
+    U = orc.init_hot(d, 6, 0)
+    orc.sweep_hb_or(d, U, 6.0, 6, 0, 0, 5)
+    f = field(m, d, "fp32")
+    m.su3_field_from_host(f, U)
+    acc, dH = m.su3_hmc_trajectory(f, 6.0, 1.0, 20, 6, 0, 0, 0)
+    racc, rdH = orc.hmc_trajectory(d, U, 6.0, 1.0, 20, 6, 0, 0, 0)
+    assert abs(dH - rdH) < 0.05 + 0.02 * abs(rdH), (dH, rdH)
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 5e-4
+
+
+def test_wilson_flow_matches_oracle(m, orc):
+    d = [4, 4, 6, 4]
+    U = orc.init_hot(d, 3, 0)
+    orc.sweep_hb_or(d, U, 6.0, 3, 0, 0, 3)
+    f = field(m, d)
+    m.su3_field_from_host(f, U)
+    m.su3_wilson_flow(f, 0.02, 5)
+    orc.wilson_flow(d, U, 0.02, 5)
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
+    assert abs(m.su3_topological_charge(f) - orc.topological_charge(d, U)) < 1e-11
+
+
+def test_restrict_and_prolongate_match_oracle(m, orc):
+    dc = [2, 4, 2, 2]
+    df = [4, 8, 4, 4]
+    Uc = orc.init_hot(dc, 7, 0)
+    orc.sweep_hb_or(dc, Uc, 5.8, 7, 0, 0, 10)
+    c = field(m, dc)
+    fine = field(m, df)
+    m.su3_field_from_host(c, Uc)
+    it = m.su3_prolongate(c, fine, 0.05, 1e-5, 10000)
+    Uf, rit = orc.prolongate(dc, Uc, 0.05, 1e-5, 10000)
+    assert it == rit
+    assert np.max(np.abs(m.su3_field_to_host(fine) - Uf)) < 1e-11
+    c2 = field(m, dc)
+    m.su3_restrict(fine, c2)
+    assert np.max(np.abs(m.su3_field_to_host(c2) - orc.restrict(df, Uf))) < 1e-14
+    assert np.max(np.abs(m.su3_field_to_host(c2) - Uc)) < 1e-14
+
+
+def test_check_field_flags_bad_links(m, orc):
+    d = [4, 4, 4, 4]
+    U = orc.init_hot(d, 1, 0)
+    f = field(m, d)
+    m.su3_field_from_host(f, U)
+    ok, dev, _ = m.su3_check_field(f, 1e-12)
+    assert ok and dev < 1e-14
+    U[37, 2, 1, 1, 0] = np.nan
+    m.su3_field_from_host(f, U)
+    ok, dev, worst = m.su3_check_field(f, 1e-12)
+    # site 37 has parity (1+1+2+0)%2 = 0, cb = 18, slab = 2*2+0
+    assert not ok and worst == 4 * (np.prod(d) // 2) + 37 // 2
+
+
+def test_full_size_32_4_fp64_sweep_matches_oracle(m, orc):
+    """32^4 in the benchmark's launch shapes: one sweep (1 HB + 1 OR) from a
+    hot start, every link compared with the oracle."""
+    d = [32, 32, 32, 32]
+    f = field(m, d)
+    m.su3_init_hot(f, 3, 0)
+    h = m.su3_sweep_hb_or(f, 6.0, 3, 0, 0, 1, P(n_or=1))
+    U = orc.init_hot(d, 3, 0)
+    href, _ = orc.sweep_hb_or(d, U, 6.0, 3, 0, 0, 1, n_or=1)
+    assert abs(h[0] - href[0]) < 1e-13
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
+
+
+def test_full_size_32_4_fp32_sweep_tracks_oracle(m, orc):
+    """32^4 FP32-R12 from the hot start, one sweep of 1 HB + 1 OR: plaquette
+    within 1e-6 of the FP64 oracle; per-link deviation median below 1e-5,
+    99.9th percentile below 1e-3 and O(1) outliers (flipped FP32 sampler
+    decisions) in at most 1 link in 10^4."""
+    d = [32, 32, 32, 32]
+    f = field(m, d, "fp32_r12")
+    m.su3_init_hot(f, 3, 0)
+    h = m.su3_sweep_hb_or(f, 6.0, 3, 0, 0, 1, P(n_or=1))
+    U = orc.init_hot(d, 3, 0)
+    href, _ = orc.sweep_hb_or(d, U, 6.0, 3, 0, 0, 1, n_or=1)
+    med, q999, mx, dev = fp32_link_stats(m.su3_field_to_host(f), U)
+    print(f"32^4 r12: plaquette diff {abs(h[0] - href[0]):.2e}, link dev median {med:.2e} q99.9 {q999:.2e} max {mx:.2e}")
+    assert abs(h[0] - href[0]) < 1e-6
+    assert med < 1e-5 and q999 < 1e-3
+    assert np.count_nonzero(dev > 1e-2) <= dev.size // 10000

@@ -180,3 +180,22 @@ def test_reunitarize_restores_su3(orc):
     orc.reunitarize(d, U)
     # a field already in SU(3) is unchanged to rounding, row 2 rebuilt from rows 0,1
     np.testing.assert_allclose(U, si.random_field(d, 4), atol=1e-14)
+
+
+def test_fixed_sequence_elementary_functions(orc):
+    """The oracle's own ln, exp and (cos, sin)(2 pi u), used for every random
+    draw, agree with the C library to a few ulp over their ranges of use."""
+    rng = np.random.Generator(np.random.PCG64(17))
+    xs = np.concatenate([rng.random(4000), 2.0 ** -rng.uniform(0, 24, 2000), [2.0**-24, 0.5, 1 - 2.0**-24, 1.0]])
+    for x in xs:
+        ref = np.log(x)
+        assert abs(orc.det_ln(x) - ref) <= 4 * np.spacing(max(abs(ref), 1e-300)) + 1e-300, x
+    for y in np.concatenate([-rng.uniform(0, 60, 3000), [0.0, -1e-12, -700.0]]):
+        ref = np.exp(y)
+        assert abs(orc.det_exp(y) - ref) <= 4 * np.spacing(ref), y
+    us = np.concatenate([rng.random(4000), [0.0, 0.125, 0.25, 0.5, 0.75, 1.0 - 2.0**-24]])
+    two_pi = 2 * np.longdouble("3.14159265358979323846264338327950288")
+    for u in us:
+        c, s = orc.det_cossin_2pi(u)
+        ang = two_pi * np.longdouble(u)  # x87 extended precision reference
+        assert abs(c - float(np.cos(ang))) < 2.3e-16 and abs(s - float(np.sin(ang))) < 2.3e-16, u
