@@ -72,8 +72,9 @@ def run_variant(m, torch, prec, n_lat, dims, steps, warmup, beta=6.0, n_or=4):
     m.su3_profile_enable(False)
     V = dims[0] * dims[1] * dims[2] * dims[3]
     updates = 5 * 4 * V * n_lat * steps if n_or == 4 else (1 + n_or) * 4 * V * n_lat * steps
+    cfg = m.su3_get_config(fields)
     out = {
-        "prec": prec, "n_lat": n_lat, "wall_s": wall, "event_ms": ev_ms,
+        "prec": prec, "n_lat": n_lat, "launch": cfg, "wall_s": wall, "event_ms": ev_ms,
         "ms_per_step": wall * 1e3 / steps, "updates_per_s": updates / wall,
         "hb_kernel_us": 1e3 * hb_ms / max(hb_n, 1), "or_kernel_us": 1e3 * or_ms / max(or_n, 1),
         "hb_launches": hb_n, "or_launches": or_n, "plaq_last": float(plaq[-1].mean()),
@@ -131,6 +132,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", help="comma list of variants to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -147,6 +149,7 @@ def main():
         return
     L = a.lattice
     dims = [L, L, L, L]
+    m.su3_autotune(not a.no_tune)
     want = set(a.only.split(",")) if a.only else {"fp64", "fp32", "fp32_r12", "fp32_batch", "r12_batch"}
     res = {}
     plan = [("fp64", "fp64", 1), ("fp32", "fp32", 1), ("fp32_r12", "fp32_r12", 1),
@@ -185,7 +188,8 @@ def main():
         "cpu_baseline": cpu,
         "variants": {k: {"link_updates_per_s": round(v["updates_per_s"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                          "or_kernel_us": round(v["or_kernel_us"], 2), "hb_kernel_us": round(v["hb_kernel_us"], 2),
-                         "or_hbm_frac": roofline(v)["frac"], "plaq_after": round(v["plaq_last"], 8)}
+                         "or_hbm_frac": roofline(v)["frac"], "plaq_after": round(v["plaq_last"], 8),
+                         "launch": v["launch"]}
                      for k, v in res.items()},
     }
     if "fp64" in res:

@@ -199,6 +199,17 @@ int32_t su3_set_launch(int32_t block, int32_t xcd_remap);
 int32_t su3_autotune(int32_t enable);
 int32_t su3_get_launch(int32_t* block, int32_t* xcd_remap);
 
+/* Site tile of the checkerboard phase kernels: threads walk each lattice in
+ * tiles of L0 x ty x tz x tt sites (each extent clamped to the largest
+ * divisor of L1, L2, L3 not above it; 0 = whole extent).  (0, 0, 0) restores
+ * the automatic choice (autotuned, else 16 x 8 x 4).  Results do not depend
+ * on it; it sets which neighbour links are loaded together into one L2. */
+int32_t su3_set_tile(int32_t ty, int32_t tz, int32_t tt);
+
+/* The launch shape the next sweep on these n fields would use:
+ * out = {block, xcd_remap, ty, tz, tt} (tile before clamping). */
+int32_t su3_get_config(const su3_field* fs, int32_t n, int32_t out[5]);
+
 /* Kernel timing with HIP events recorded on the field's stream around each
  * phase launch.  While enabled, su3_batch_sweep_hb_or launches the same
  * kernels eagerly instead of replaying its graph.  kind 0 = heat-bath

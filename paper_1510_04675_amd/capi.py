@@ -61,6 +61,8 @@ SIGNATURES = {
     "su3_set_launch": (_i32, [_i32, _i32]),
     "su3_autotune": (_i32, [_i32]),
     "su3_get_launch": (_i32, [C.POINTER(_i32), C.POINTER(_i32)]),
+    "su3_set_tile": (_i32, [_i32, _i32, _i32]),
+    "su3_get_config": (_i32, [_p, _i32, _p]),
     "su3_profile_enable": (_i32, [_i32]),
     "su3_profile_read": (_i32, [_i32, C.POINTER(_d), C.POINTER(_i64)]),
     "su3_last_error": (C.c_char_p, []),
@@ -293,6 +295,19 @@ def su3_get_launch():
     b, r = C.c_int32(), C.c_int32()
     _ck(lib().su3_get_launch(C.byref(b), C.byref(r)))
     return b.value, r.value
+
+
+def su3_set_tile(ty: int, tz: int, tt: int):
+    _ck(lib().su3_set_tile(ty, tz, tt))
+
+
+def su3_get_config(fields):
+    """{block, xcd_remap, ty, tz, tt} the next sweep on these fields uses."""
+    n = len(fields)
+    hs = (C.c_void_p * n)(*[f.handle.value for f in fields])
+    out = (C.c_int32 * 5)()
+    _ck(lib().su3_get_config(hs, n, out))
+    return dict(zip(("block", "xcd_remap", "ty", "tz", "tt"), list(out)))
 
 
 def su3_autotune(enable: bool):

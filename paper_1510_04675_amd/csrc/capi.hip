@@ -102,20 +102,50 @@ static hipError_t upload_ints(int* dst, const std::vector<int>& src, hipStream_t
 // ---------------------------------------------------------------------------
 // Fields
 // ---------------------------------------------------------------------------
-static size_t padded_stride(size_t n, size_t elem)
+// Bytes of one slab (one direction and parity) of Vh records of nreal reals
+// of rb bytes each: whole tiles of 32 records, rounded up to an odd number
+// of 256-byte blocks so that the slabs of one site do not all fall into the
+// same cache sets.
+static size_t slab_bytes(size_t Vh, int nreal, size_t rb)
 {
-    size_t lines = (n * elem + 127) / 128;
-    if (lines == 0) lines = 1;
-    if ((lines & 1) == 0) lines += 1;
-    return lines * 128 / elem;
+    const size_t tiles = (Vh + 31) / 32;
+    size_t blocks = (tiles * 32 * (size_t)nreal * rb + 255) / 256;
+    if (blocks == 0) blocks = 1;
+    if ((blocks & 1) == 0) blocks += 1;
+    return blocks * 256;
 }
 
 struct su3_field_s;
+
+// Launch shape of the phase kernels: block size, XCD remapping and the
+// requested site tile (ty, tz, tt; 0 = whole extent, clamped per lattice to
+// the largest divisor not above the request).
+struct LaunchCfg {
+    int block = 256, remap = 1, ty = 0, tz = 0, tt = 1;
+    bool operator==(const LaunchCfg& o) const
+    {
+        return block == o.block && remap == o.remap && ty == o.ty && tz == o.tz && tt == o.tt;
+    }
+    std::string str() const
+    {
+        return std::to_string(block) + "," + std::to_string(remap) + "," + std::to_string(ty) + "," +
+               std::to_string(tz) + "," + std::to_string(tt);
+    }
+};
+
+static int largest_divisor_upto(int L, int want)
+{
+    if (want <= 0 || want >= L) return L;
+    for (int t = want; t >= 1; t--)
+        if (L % t == 0) return t;
+    return 1;
+}
 
 // Device tables for a set of lattices of one precision.
 struct Plan {
     int nlat = 0;
     int prec = 0;
+    LaunchCfg cfg;
     int phase_block = 256, remap = 1;
     LatDesc* d_descs = nullptr;  // nlat entries
     int* d_bbeg_phase = nullptr;
@@ -202,10 +232,10 @@ static void layout(const int32_t* dims, int prec, size_t& cs, size_t& cs8, size_
     long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
     const size_t Vh = (size_t)(V / 2);
     const size_t rb = prec_real_bytes(prec);
-    cs = padded_stride(Vh, rb);
-    cs8 = padded_stride(Vh, rb);
-    bytes = 8 * (size_t)prec_ncomp(prec) * cs * rb;
-    bytes8 = 8 * 8 * cs8 * rb;
+    cs = slab_bytes(Vh, prec_ncomp(prec), rb);
+    cs8 = slab_bytes(Vh, 8, rb);
+    bytes = 8 * cs;
+    bytes8 = 8 * cs8;
 }
 
 static int32_t check_field(su3_field f)
@@ -230,21 +260,27 @@ static LatDesc base_desc(const su3_field_s* f)
 static int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 // Build or rebuild the device tables of a plan for the given fields.
-static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, int phase_block, int remap,
-                          int out_cap, hipStream_t st)
+static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const LaunchCfg& cfg, int out_cap,
+                          hipStream_t st)
 {
     const bool shape_change = p.nlat != (int)fs.size();
     if (shape_change) p.release();
+    const int phase_block = cfg.block;
     p.nlat = (int)fs.size();
     p.prec = fs[0]->prec;
+    p.cfg = cfg;
     p.phase_block = phase_block;
-    p.remap = remap;
+    p.remap = cfg.remap;
     p.host_descs.clear();
     p.bbeg_phase_h.assign(1, 0);
     p.bbeg_link_h.assign(1, 0);
     p.bbeg_site_h.assign(1, 0);
     for (auto* f : fs) {
-        p.host_descs.push_back(base_desc(f));
+        LatDesc d = base_desc(f);
+        d.tile[0] = largest_divisor_upto(f->L[1], cfg.ty);
+        d.tile[1] = largest_divisor_upto(f->L[2], cfg.tz);
+        d.tile[2] = largest_divisor_upto(f->L[3], cfg.tt);
+        p.host_descs.push_back(d);
         p.bbeg_phase_h.push_back(p.bbeg_phase_h.back() + ceil_div(f->Vh, phase_block));
         p.bbeg_link_h.push_back(p.bbeg_link_h.back() + ceil_div(8LL * f->Vh, 256));
         p.bbeg_site_h.push_back(p.bbeg_site_h.back() + ceil_div(2LL * f->Vh, 256));
@@ -279,8 +315,10 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, int phas
 // ---------------------------------------------------------------------------
 static std::mutex g_mu;
 static int g_forced_block = 0, g_forced_remap = 1;
+static int g_forced_tile[3] = { 0, 0, 0 };
+static bool g_tile_forced = false;
 static bool g_autotune = false;
-static std::map<std::string, std::pair<int, int>> g_tuned;
+static std::map<std::string, LaunchCfg> g_tuned;
 static bool g_profile = false;
 static double g_prof_ms[2] = { 0, 0 };
 static long long g_prof_n[2] = { 0, 0 };
@@ -294,22 +332,34 @@ static std::string shape_key(const std::vector<su3_field_s*>& fs)
     return k;
 }
 
-static void launch_choice(const std::vector<su3_field_s*>& fs, int& block, int& remap)
+// Default tile: 16 x 8 x 4 sites in (y, z, t) when the extents allow it.
+static LaunchCfg default_cfg()
+{
+    LaunchCfg c;
+    c.block = 256;
+    c.remap = 1;
+    c.ty = 16;
+    c.tz = 8;
+    c.tt = 4;
+    return c;
+}
+
+static LaunchCfg launch_choice(const std::vector<su3_field_s*>& fs)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_forced_block > 0) {
-        block = g_forced_block;
-        remap = g_forced_remap;
-        return;
-    }
+    LaunchCfg c = default_cfg();
     auto it = g_tuned.find(shape_key(fs));
-    if (it != g_tuned.end()) {
-        block = it->second.first;
-        remap = it->second.second;
-        return;
+    if (it != g_tuned.end()) c = it->second;
+    if (g_forced_block > 0) {
+        c.block = g_forced_block;
+        c.remap = g_forced_remap;
     }
-    block = 256;
-    remap = 1;
+    if (g_tile_forced) {
+        c.ty = g_forced_tile[0];
+        c.tz = g_forced_tile[1];
+        c.tt = g_forced_tile[2];
+    }
+    return c;
 }
 
 static int32_t ensure_events(size_t n)
@@ -402,17 +452,30 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
         sp.push_back(&scratch[i]);
     }
     Plan p;
-    const int blocks[] = { 64, 128, 256, 512 };
+    std::vector<LaunchCfg> cand;
+    const int blocks[] = { 128, 256, 512 };
+    const int tiles[][3] = { { 0, 0, 1 }, { 16, 8, 4 }, { 16, 16, 4 }, { 8, 8, 8 }, { 16, 8, 8 }, { 32, 8, 4 }, { 8, 8, 16 } };
+    for (int remap = 0; remap < 2; remap++)
+        for (int b : blocks)
+            for (auto& t : tiles) {
+                LaunchCfg c;
+                c.block = b;
+                c.remap = remap;
+                c.ty = t[0];
+                c.tz = t[1];
+                c.tt = t[2];
+                cand.push_back(c);
+            }
     float best = 1e30f;
-    int bb = 256, br = 1;
+    LaunchCfg bestc = default_cfg();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = fail(SU3_ERR_HIP, "event creation failed");
-    for (int bi = 0; bi < 4 && !rc; bi++)
-        for (int remap = 0; remap < 2 && !rc; remap++) {
-            rc = plan_build(p, sp, blocks[bi], remap, 1, st);
+    for (size_t ci = 0; ci < cand.size() && !rc; ci++) {
+        {
+            rc = plan_build(p, sp, cand[ci], 1, st);
             if (rc) break;
-            if (bi == 0 && remap == 0) {
+            if (ci == 0) {
                 for (size_t i = 0; i < sp.size(); i++) p.host_descs[i].seed = 12345u + (uint32_t)i;
                 if (upload_descs(p.d_descs, p.host_descs, st) != hipSuccess ||
                     launch_init(p.prec, 1, p.grid_link(), st) != hipSuccess) {
@@ -436,10 +499,10 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
             hipEventElapsedTime(&ms, e0, e1);
             if (ms < best) {
                 best = ms;
-                bb = blocks[bi];
-                br = remap;
+                bestc = cand[ci];
             }
         }
+    }
     hipStreamSynchronize(st);
     p.release();
     for (auto& s : scratch) hipFree(s.data);
@@ -447,7 +510,7 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
     if (e1) hipEventDestroy(e1);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tuned[shape_key(fs)] = { bb, br };
+    g_tuned[shape_key(fs)] = bestc;
     return SU3_OK;
 }
 
@@ -514,13 +577,11 @@ static void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1)
 // ---------------------------------------------------------------------------
 static int32_t single_plan(su3_field_s* f, int out_cap)
 {
-    int block, remap;
     std::vector<su3_field_s*> fs{ f };
-    launch_choice(fs, block, remap);
-    if (!f->plan_ready || f->plan.phase_block != block || f->plan.remap != remap || f->plan.out_cap < out_cap ||
-        f->plan.host_descs.empty() || f->plan.host_descs[0].aux != f->aux8 ||
-        f->plan.host_descs[0].aux2 != f->alt[0]) {
-        int32_t rc = plan_build(f->plan, fs, block, remap, std::max(out_cap, 8), f->stream);
+    const LaunchCfg cfg = launch_choice(fs);
+    if (!f->plan_ready || !(f->plan.cfg == cfg) || f->plan.out_cap < out_cap || f->plan.host_descs.empty() ||
+        f->plan.host_descs[0].aux != f->aux8 || f->plan.host_descs[0].aux2 != f->alt[0]) {
+        int32_t rc = plan_build(f->plan, fs, cfg, std::max(out_cap, 8), f->stream);
         if (rc) return rc;
         f->plan_ready = true;
     }
@@ -673,7 +734,7 @@ int32_t su3_init_hot(su3_field f, uint32_t seed, uint32_t lattice_id)
     int32_t rc = check_field(f);
     if (!rc) rc = single_plan(f, 1);
     if (rc) return rc;
-    std::vector<LatDesc> d{ base_desc(f) };
+    std::vector<LatDesc> d{ f->plan.host_descs[0] };
     d[0].seed = seed;
     d[0].lid = lattice_id;
     HIPCHK(upload_descs(f->plan.d_descs, d, f->stream));
@@ -746,7 +807,7 @@ int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattic
     }
     if ((rc = single_plan(f, std::max(1, n_sweeps)))) return rc;
     Plan& p = f->plan;
-    std::vector<LatDesc> d{ base_desc(f) };
+    std::vector<LatDesc> d{ p.host_descs[0] };
     d[0].beta = beta;
     d[0].seed = seed;
     d[0].lid = lattice_id;
@@ -810,12 +871,10 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
         }
         if (!have && (rc = autotune(v, st))) return rc;
     }
-    int block, remap;
-    launch_choice(v, block, remap);
+    const LaunchCfg cfg = launch_choice(v);
     std::string key = std::to_string(n_sweeps) + "|" + std::to_string(o.n_or) + "," + std::to_string(o.n_hits) +
                       "," + std::to_string(o.max_tries) + "," + std::to_string(o.reunit_every) + "," +
-                      std::to_string(o.sampler) + "," + std::to_string(o.record) + "|" + std::to_string(block) +
-                      "," + std::to_string(remap) + "|";
+                      std::to_string(o.sampler) + "," + std::to_string(o.record) + "|" + cfg.str() + "|";
     for (auto* f : v) {
         char buf[64];
         snprintf(buf, sizeof buf, "%p,", (void*)f);
@@ -833,7 +892,7 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
         ge = new GraphEntry();
         ge->key = key;
         ge->fields = v;
-        rc = plan_build(ge->plan, v, block, remap, n_sweeps * n, st);
+        rc = plan_build(ge->plan, v, cfg, n_sweeps * n, st);
         if (rc) {
             drop_graph(ge);
             return rc;
@@ -845,7 +904,7 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
         ge = new GraphEntry();
         ge->key = key;
         ge->fields = v;
-        rc = plan_build(ge->plan, v, block, remap, n_sweeps * n, st);
+        rc = plan_build(ge->plan, v, cfg, n_sweeps * n, st);
         if (!rc && hipStreamCreateWithFlags(&ge->capture, hipStreamNonBlocking) != hipSuccess)
             rc = fail(SU3_ERR_HIP, "capture stream creation failed");
         if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(SU3_ERR_HIP, "stream sync failed");
@@ -878,7 +937,6 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
     }
     Plan& p = ge->plan;
     for (int i = 0; i < n; i++) {
-        p.host_descs[i] = base_desc(v[i]);
         p.host_descs[i].beta = betas[i];
         p.host_descs[i].seed = seeds[i];
         p.host_descs[i].lid = lattice_ids[i];
@@ -1163,8 +1221,8 @@ int32_t su3_prolongate(su3_field coarse, su3_field fine, double c, double rel_to
     hipStream_t st = fine->stream;
     if (coarse->stream != st) HIPCHK(hipStreamSynchronize(coarse->stream));
     const Geo gf = fine->geo();
-    const size_t csf = padded_stride(fine->Vh, 8);
-    const size_t nbytes = 8 * 18 * csf * 8;
+    const size_t csf = slab_bytes(fine->Vh, 18, 8);
+    const size_t nbytes = 8 * csf;
     double* buf[2] = { nullptr, nullptr };
     const int nb = ceil_div(2LL * fine->Vh, 256);
     double* bs = nullptr;
@@ -1223,6 +1281,34 @@ int32_t su3_set_launch(int32_t block, int32_t xcd_remap)
     std::lock_guard<std::mutex> lk(g_mu);
     g_forced_block = block;
     g_forced_remap = xcd_remap;
+    return SU3_OK;
+}
+
+int32_t su3_set_tile(int32_t ty, int32_t tz, int32_t tt)
+{
+    if (ty < 0 || tz < 0 || tt < 0) return fail(SU3_ERR_ARG, "tile extents must be >= 0");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tile_forced = !(ty == 0 && tz == 0 && tt == 0);
+    g_forced_tile[0] = ty;
+    g_forced_tile[1] = tz;
+    g_forced_tile[2] = tt;
+    return SU3_OK;
+}
+
+int32_t su3_get_config(const su3_field* fs, int32_t n, int32_t out[5])
+{
+    if (!fs || n <= 0 || !out) return fail(SU3_ERR_ARG, "need fields and an output array");
+    std::vector<su3_field_s*> v;
+    for (int i = 0; i < n; i++) {
+        if (!fs[i]) return fail(SU3_ERR_ARG, "NULL field");
+        v.push_back(fs[i]);
+    }
+    const LaunchCfg c = launch_choice(v);
+    out[0] = c.block;
+    out[1] = c.remap;
+    out[2] = c.ty;
+    out[3] = c.tz;
+    out[4] = c.tt;
     return SU3_OK;
 }
 

@@ -1,18 +1,17 @@
 // device.hpp -- device-side building blocks for the SU(3) rethermalization
-// kernels on gfx950: SU(3) matrices in registers, the structure-of-arrays
-// link layout, checkerboard geometry and the Philox4x32-10 generator.
+// kernels on gfx950: SU(3) matrices in registers, the tiled link layout,
+// checkerboard geometry, the Philox4x32-10 generator and the fixed-sequence
+// fp64 elementary functions.
 //
-// Link layout (one allocation per lattice):
-//   element (mu, parity, component, cb) at
-//     base[((mu * 2 + parity) * NC + component) * cs + cb]
-//   NC = 18 (full matrix) or 12 (rows 0 and 1; row 2 rebuilt on load),
-//   component = (row * 3 + col) * 2 + {0: re, 1: im},
-//   cb = checkerboard index = (lexicographic site index) >> 1,
-//   cs = component stride >= V/2, padded so that cs * sizeof(real) is an
-//        odd number of 128-byte lines (component arrays of one link do not
-//        alias in the same L2 sets).
-// Consecutive threads take consecutive cb, so every component load of a
-// wavefront is one contiguous 256 B (fp32) or 512 B (fp64) segment.
+// Link layout (one allocation per lattice): 8 slabs, slab = mu * 2 + parity,
+// each holding the V/2 link records of that direction and parity indexed by
+// cb = (lexicographic site index) >> 1.  A record is NC reals, NC = 18 (full
+// matrix) or 12 (rows 0 and 1; row 2 rebuilt on load), ordered (re, im) per
+// entry, row-major.  Records are grouped in tiles of 32 consecutive cb and
+// cut into 16-byte chunks; chunk c of the 32 records of a tile is contiguous
+// (see load_reals).  A thread loads a record with 16-byte vector loads at
+// fixed offsets from one address; a wavefront's load covers contiguous
+// 512-byte runs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -511,31 +510,106 @@ __device__ __forceinline__ void mul2_c(const Cx a[2][2], const Cx b[2][2], Cx c[
 // ---------------------------------------------------------------------------
 // Link field views.
 // ---------------------------------------------------------------------------
-template <typename R, int NC> struct Links {
-    R* p;
-    size_t cs;  // component stride in elements
-    __device__ __forceinline__ R* slab(int mu, int par) const { return p + (size_t)((mu * 2 + par) * NC) * cs; }
+// Records of N reals (a link: N = 18 or 12; momenta / flow generators:
+// N = 8) live in slabs, one per (direction, parity), sb bytes apart.  A slab
+// is a sequence of tiles of 32 consecutive checkerboard sites; inside a tile
+// the records are cut into 16-byte chunks and chunk c of all 32 sites is
+// contiguous (512 bytes), followed by an 8-byte tail chunk (256 bytes) when
+// the record is not a multiple of 16 bytes (fp32, N = 18).  Record reals are
+// ordered (re, im) per matrix entry, row-major.  A thread computes one
+// address per record and loads it with 16-byte vector loads at fixed
+// offsets; a wavefront's load is two or three contiguous 512-byte runs.
+// ---------------------------------------------------------------------------
+template <typename R, int N> struct Rec {
+    static constexpr int BYTES = N * (int)sizeof(R);
+    static constexpr int NF = BYTES / 16;
+    static constexpr bool TAIL = (BYTES % 16) != 0;
+    static constexpr int TB = 32 * BYTES;
 };
 
-template <typename R, int NC> __device__ __forceinline__ M3<R> load_link(const R* __restrict__ s, size_t cs, int cb)
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) v4f g_v4f;
+typedef __attribute__((address_space(1))) v2f g_v2f;
+typedef __attribute__((address_space(1))) v2d g_v2d;
+
+template <typename R, int N> __device__ __forceinline__ void load_reals(uintptr_t slab, int cb, R out[N])
 {
+    using L = Rec<R, N>;
+    const uintptr_t t = slab + (uintptr_t)(cb >> 5) * L::TB;
+    const uintptr_t q = t + (uintptr_t)(cb & 31) * 16;
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int c = 0; c < L::NF; c++) {
+            const v4f v = *(const g_v4f*)(q + c * 512);
+            out[4 * c] = v.x;
+            out[4 * c + 1] = v.y;
+            out[4 * c + 2] = v.z;
+            out[4 * c + 3] = v.w;
+        }
+        if constexpr (L::TAIL) {
+            const v2f v = *(const g_v2f*)(t + L::NF * 512 + (uintptr_t)(cb & 31) * 8);
+            out[4 * L::NF] = v.x;
+            out[4 * L::NF + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < L::NF; c++) {
+            const v2d v = *(const g_v2d*)(q + c * 512);
+            out[2 * c] = v.x;
+            out[2 * c + 1] = v.y;
+        }
+    }
+}
+
+template <typename R, int N> __device__ __forceinline__ void store_reals(uintptr_t slab, int cb, const R in[N])
+{
+    using L = Rec<R, N>;
+    const uintptr_t t = slab + (uintptr_t)(cb >> 5) * L::TB;
+    const uintptr_t q = t + (uintptr_t)(cb & 31) * 16;
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int c = 0; c < L::NF; c++)
+            *(g_v4f*)(q + c * 512) = v4f{ in[4 * c], in[4 * c + 1], in[4 * c + 2], in[4 * c + 3] };
+        if constexpr (L::TAIL)
+            *(g_v2f*)(t + L::NF * 512 + (uintptr_t)(cb & 31) * 8) = v2f{ in[4 * L::NF], in[4 * L::NF + 1] };
+    } else {
+#pragma unroll
+        for (int c = 0; c < L::NF; c++) *(g_v2d*)(q + c * 512) = v2d{ in[2 * c], in[2 * c + 1] };
+    }
+}
+
+template <typename R, int NC> struct Links {
+    uintptr_t p;
+    size_t sb;  // bytes per slab
+    __device__ __forceinline__ uintptr_t slab(int mu, int par) const { return p + (uintptr_t)(mu * 2 + par) * sb; }
+    __device__ __forceinline__ uintptr_t slab_at(int s) const { return p + (uintptr_t)s * sb; }
+};
+
+template <typename R, int NC> __device__ __forceinline__ M3<R> load_link(uintptr_t slab, int cb)
+{
+    R b[NC];
+    load_reals<R, NC>(slab, cb, b);
     M3<R> m;
 #pragma unroll
-    for (int k = 0; k < (NC == 18 ? 9 : 6); k++) {
-        m.re[k] = s[(size_t)(2 * k) * cs + cb];
-        m.im[k] = s[(size_t)(2 * k + 1) * cs + cb];
+    for (int k = 0; k < NC / 2; k++) {
+        m.re[k] = b[2 * k];
+        m.im[k] = b[2 * k + 1];
     }
-    if (NC == 12) m_complete_row2(m);
+    if constexpr (NC == 12) m_complete_row2(m);
     return m;
 }
 
-template <typename R, int NC> __device__ __forceinline__ void store_link(R* __restrict__ s, size_t cs, int cb, const M3<R>& m)
+template <typename R, int NC> __device__ __forceinline__ void store_link(uintptr_t slab, int cb, const M3<R>& m)
 {
+    R b[NC];
 #pragma unroll
-    for (int k = 0; k < (NC == 18 ? 9 : 6); k++) {
-        s[(size_t)(2 * k) * cs + cb] = m.re[k];
-        s[(size_t)(2 * k + 1) * cs + cb] = m.im[k];
+    for (int k = 0; k < NC / 2; k++) {
+        b[2 * k] = m.re[k];
+        b[2 * k + 1] = m.im[k];
     }
+    store_reals<R, NC>(slab, cb, b);
 }
 
 // Convenience: load U_mu at site coordinates n (any parity).
@@ -543,7 +617,7 @@ template <typename R, int NC> __device__ __forceinline__ M3<R> load_at(const Lin
 {
     int i = lex_index(g, n);
     int par = (n[0] + n[1] + n[2] + n[3]) & 1;
-    return load_link<R, NC>(U.slab(mu, par), U.cs, i >> 1);
+    return load_link<R, NC>(U.slab(mu, par), i >> 1);
 }
 
 // Staple sum A_mu(n): for nu != mu ascending, the forward term

@@ -39,11 +39,11 @@ __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double 
     const int e = (lb - gr.bbeg[l]) * (int)blockDim.x + (int)threadIdx.x;
     if (e >= 8 * Vh) return;
     const int slab = e / Vh, cb = e - slab * Vh, mu = slab >> 1, par = slab & 1;
-    const Links<R, NC> W{ (R*)d.U, d.cs };
+    const Links<R, NC> W{ (uintptr_t)d.U, d.cs };
     int n[4];
     cb_coords(d.g, cb, par, n);
     const M3<R> A = staple_sum<R, NC, R>(W, d.g, mu, n);
-    const M3<R> w = load_link<R, NC>(W.slab(mu, par), W.cs, cb);
+    const M3<R> w = load_link<R, NC>(W.slab(mu, par), cb);
     const M3<R> Om = m_mul(w, A);
     // Z in 8-real form
     const R tr3 = (Om.im[0] + Om.im[4] + Om.im[8]) / R(3);
@@ -56,15 +56,16 @@ __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double 
     z[5] = R(-0.5) * (Om.im[2] + Om.im[6]);
     z[6] = R(-0.5) * (Om.re[5] - Om.re[7]);
     z[7] = R(-0.5) * (Om.im[5] + Om.im[7]);
-    R* xp = (R*)d.aux + (size_t)(slab * 8) * d.cs8 + cb;
-    R x[8];
+    const uintptr_t xslab = (uintptr_t)d.aux + (uintptr_t)slab * d.cs8;
+    R x[8], xo[8];
     const R fz = (R)(cz * eps), fa = (R)ca;
+    if (!first) load_reals<R, 8>(xslab, cb, xo);
 #pragma unroll
     for (int a = 0; a < 8; a++) {
         x[a] = fz * z[a];
-        if (!first) x[a] += fa * xp[(size_t)a * d.cs8];
-        xp[(size_t)a * d.cs8] = x[a];
+        if (!first) x[a] += fa * xo[a];
     }
+    store_reals<R, 8>(xslab, cb, x);
     M3<R> X;
     X.re[0] = R(0);
     X.im[0] = x[0];
@@ -85,8 +86,8 @@ __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double 
     X.re[7] = -x[6];
     X.im[7] = x[7];
     const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N>(X);
-    const Links<R, NC> D{ (R*)d.aux2, d.cs };
-    store_link<R, NC>(D.slab(mu, par), D.cs, cb, m_mul(E, w));
+    const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
+    store_link<R, NC>(D.slab(mu, par), cb, m_mul(E, w));
 }
 
 hipError_t launch_flow_stage(int prec, const Grid& gr, double eps, double cz, double ca, int first, hipStream_t st)

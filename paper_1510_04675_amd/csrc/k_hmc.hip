@@ -3,7 +3,8 @@
 //
 // Momenta: p^a, a = 1..8, per link, P = sum_a p^a lambda^a / 2, stored as 8
 // reals per link in the same structure-of-arrays scheme as the links:
-// element (mu, parity, a, cb) at aux[((mu*2 + parity)*8 + a)*cs8 + cb].
+// one 8-real record per link in the tiled record layout (slabs cs8 bytes
+// apart), p^1..p^8 in order.
 // Equations of motion dU/dtau = i P U, dp^a/dtau = -F^a with
 // F^a = dS/d omega^a = (beta/6) Im Tr(lambda^a U A) for U -> exp(i omega T) U.
 //
@@ -58,9 +59,10 @@ template <typename R> __global__ void __launch_bounds__(256) k_mom(Grid gr, uint
     double z[8];
     normals4<double>(rng.draw(ctr_word(P_MOM, x.mu, 0, 0, 0)), z);
     normals4<double>(rng.draw(ctr_word(P_MOM, x.mu, 0, 0, 1)), z + 4);
-    R* p = (R*)d.aux + (size_t)((x.mu * 2 + x.par) * 8) * d.cs8 + x.cb;
+    R p[8];
 #pragma unroll
-    for (int a = 0; a < 8; a++) p[(size_t)a * d.cs8] = (R)z[a];
+    for (int a = 0; a < 8; a++) p[a] = (R)z[a];
+    store_reals<R, 8>((uintptr_t)d.aux + (uintptr_t)(x.mu * 2 + x.par) * d.cs8, x.cb, p);
 }
 
 // i eps P as a 3x3 matrix (anti-hermitian, traceless)
@@ -106,11 +108,11 @@ __global__ void __launch_bounds__(256) k_kick_drift(Grid gr, double eps_kick, do
     const LinkIdxH x = link_index_h(gr);
     if (!x.valid) return;
     const LatDesc& d = gr.descs[x.l];
-    const Links<R, NC> U{ (R*)d.U, d.cs };
+    const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
     int n[4];
     cb_coords(d.g, x.cb, x.par, n);
     const M3<R> A = staple_sum<R, NC, R>(U, d.g, x.mu, n);
-    const M3<R> u = load_link<R, NC>(U.slab(x.mu, x.par), U.cs, x.cb);
+    const M3<R> u = load_link<R, NC>(U.slab(x.mu, x.par), x.cb);
     const M3<R> Om = m_mul(u, A);
     const R b6 = (R)(d.beta / 6.0);
     const R s3 = R(0.57735026918962576451);
@@ -123,18 +125,17 @@ __global__ void __launch_bounds__(256) k_kick_drift(Grid gr, double eps_kick, do
     F[5] = b6 * (Om.im[5] + Om.im[7]);
     F[6] = b6 * (Om.re[5] - Om.re[7]);
     F[7] = b6 * s3 * (Om.im[0] + Om.im[4] - R(2) * Om.im[8]);
-    R* pp = (R*)d.aux + (size_t)((x.mu * 2 + x.par) * 8) * d.cs8 + x.cb;
+    const uintptr_t pslab = (uintptr_t)d.aux + (uintptr_t)(x.mu * 2 + x.par) * d.cs8;
     R p[8];
+    load_reals<R, 8>(pslab, x.cb, p);
     const R ek = (R)eps_kick;
 #pragma unroll
-    for (int a = 0; a < 8; a++) {
-        p[a] = pp[(size_t)a * d.cs8] - ek * F[a];
-        pp[(size_t)a * d.cs8] = p[a];
-    }
+    for (int a = 0; a < 8; a++) p[a] = p[a] - ek * F[a];
+    store_reals<R, 8>(pslab, x.cb, p);
     if (drift) {
         const M3<R> E = m_exp_ah<R, ExpOrder<R>::N>(i_eps_P(p, (R)eps_drift));
-        const Links<R, NC> D{ (R*)d.aux2, d.cs };
-        store_link<R, NC>(D.slab(x.mu, x.par), D.cs, x.cb, m_mul(E, u));
+        const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
+        store_link<R, NC>(D.slab(x.mu, x.par), x.cb, m_mul(E, u));
     }
 }
 
@@ -160,10 +161,11 @@ template <typename R> __global__ void __launch_bounds__(256) k_kinetic(Grid gr, 
     double k = 0.0;
     if (e < 8 * d.g.Vh) {
         const int slab = e / d.g.Vh, cb = e - slab * d.g.Vh;
-        const R* pp = (const R*)d.aux + (size_t)(slab * 8) * d.cs8 + cb;
+        R pv[8];
+        load_reals<R, 8>((uintptr_t)d.aux + (uintptr_t)slab * d.cs8, cb, pv);
 #pragma unroll
         for (int a = 0; a < 8; a++) {
-            const double v = (double)pp[(size_t)a * d.cs8];
+            const double v = (double)pv[a];
             k += 0.5 * v * v;
         }
     }

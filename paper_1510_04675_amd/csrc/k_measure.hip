@@ -77,7 +77,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_plaq(Grid
     double acc = 0.0;
     if (s.valid) {
         const LatDesc& d = gr.descs[s.l];
-        const Links<R, NC> U{ (R*)d.U, d.cs };
+        const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
 #pragma unroll
         for (int mu = 0; mu < 4; mu++) {
             int npm[4];
@@ -166,7 +166,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_qtop(Grid
     double acc = 0.0;
     if (s.valid) {
         const LatDesc& d = gr.descs[s.l];
-        const Links<R, NC> U{ (R*)d.U, d.cs };
+        const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
         double t = 0.0;
         {
             const M3<double> a = clover_F(U, d.g, s.n, 0, 1);
@@ -196,7 +196,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_energy(Gr
     double acc = 0.0;
     if (s.valid) {
         const LatDesc& d = gr.descs[s.l];
-        const Links<R, NC> U{ (R*)d.U, d.cs };
+        const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
         for (int mu = 0; mu < 4; mu++)
             for (int nu = mu + 1; nu < 4; nu++) {
                 const M3<double> F = clover_F(U, d.g, s.n, mu, nu);

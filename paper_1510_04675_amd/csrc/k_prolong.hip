@@ -40,12 +40,12 @@ __global__ void __launch_bounds__(256) k_restrict(Geo gf, const RF* __restrict__
     int mu, par, cb, nc[4];
     link_of(gc, e, mu, par, cb, nc);
     int nf[4] = { 2 * nc[0], 2 * nc[1], 2 * nc[2], 2 * nc[3] };
-    const Links<RF, NF> F{ (RF*)Uf, csf };
+    const Links<RF, NF> F{ (uintptr_t)Uf, csf };
     const M3<double> a = m_cast<RF, double>(load_at(F, gf, mu, nf));
     nf[mu] = wrap_add(nf[mu], 1, gf.L[mu]);
     const M3<double> b = m_cast<RF, double>(load_at(F, gf, mu, nf));
-    const Links<RC, NCc> C{ Uc, csc };
-    store_link<RC, NCc>(C.slab(mu, par), csc, cb, m_cast<double, RC>(m_mul(a, b)));
+    const Links<RC, NCc> C{ (uintptr_t)Uc, csc };
+    store_link<RC, NCc>(C.slab(mu, par), cb, m_cast<double, RC>(m_mul(a, b)));
 }
 
 // Fine bond U^f_mu(n) = U^c_mu(n/2) where all coordinates of n are even, 1 elsewhere.
@@ -60,12 +60,12 @@ __global__ void __launch_bounds__(256) k_transfer(Geo gc, const RC* __restrict__
     M3<double> m;
     if (((n[0] | n[1] | n[2] | n[3]) & 1) == 0) {
         const int nc[4] = { n[0] >> 1, n[1] >> 1, n[2] >> 1, n[3] >> 1 };
-        const Links<RC, NCc> C{ (RC*)Uc, csc };
+        const Links<RC, NCc> C{ (uintptr_t)Uc, csc };
         m = m_cast<RC, double>(load_at(C, gc, mu, nc));
     } else {
         m_set_one(m);
     }
-    store_link<double, 18>(Uf + (size_t)((mu * 2 + par) * 18) * csf, csf, cb, m);
+    store_link<double, 18>((uintptr_t)Uf + (uintptr_t)(mu * 2 + par) * csf, cb, m);
 }
 
 // Re Tr(X^+ M) summed as the trace of the product X^+ M: diagonal element r
@@ -123,11 +123,11 @@ __global__ void __launch_bounds__(256) k_ape(Geo g, const double* __restrict__ U
     if (e >= 8 * g.Vh) return;
     int mu, par, cb, n[4];
     link_of(g, e, mu, par, cb, n);
-    const Links<double, 18> U{ (double*)Uold, cs };
-    const M3<double> u = load_link<double, 18>(U.slab(mu, par), cs, cb);
-    double* dst = Unew + (size_t)((mu * 2 + par) * 18) * cs;
+    const Links<double, 18> U{ (uintptr_t)Uold, cs };
+    const M3<double> u = load_link<double, 18>(U.slab(mu, par), cb);
+    const uintptr_t dst = (uintptr_t)Unew + (uintptr_t)(mu * 2 + par) * cs;
     if (n_odd_excl(n, mu, mu) != d + 1) {
-        store_link<double, 18>(dst, cs, cb, u);
+        store_link<double, 18>(dst, cb, u);
         return;
     }
     // M = U + c (T+ + T-) added direction by direction, nu ascending
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(256) k_ape(Geo g, const double* __restrict__ U
             M.im[k] += T.im[k] * c;
         }
     }
-    store_link<double, 18>(dst, cs, cb, project_su3(M));
+    store_link<double, 18>(dst, cb, project_su3(M));
 }
 
 __device__ __forceinline__ double block_sum_256p(double v)
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256) k_partial_action(Geo g, const double* __r
         const int par = e >= g.Vh ? 1 : 0;
         int n[4];
         cb_coords(g, e - par * g.Vh, par, n);
-        const Links<double, 18> U{ (double*)Ud, cs };
+        const Links<double, 18> U{ (uintptr_t)Ud, cs };
         for (int mu = 0; mu < 4; mu++)
             for (int nu = mu + 1; nu < 4; nu++) {
                 if (n_odd_excl(n, mu, nu) != d) continue;

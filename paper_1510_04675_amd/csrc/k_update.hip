@@ -79,7 +79,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_init(Grid
     const LinkIdx x = link_index(gr);
     if (!x.valid) return;
     const LatDesc& d = gr.descs[x.l];
-    const Links<R, NC> U{ (R*)d.U, d.cs };
+    const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
     M3<double> m;
     if (hot) {
         int n[4];
@@ -89,7 +89,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_init(Grid
     } else {
         m_set_one(m);
     }
-    store_link<R, NC>(U.slab(x.mu, x.par), U.cs, x.cb, m_cast<double, R>(m));
+    store_link<R, NC>(U.slab(x.mu, x.par), x.cb, m_cast<double, R>(m));
 }
 
 template <typename R, int NC>
@@ -103,11 +103,11 @@ __global__ void __launch_bounds__(256) k_reunit(Grid gr, const uint64_t* __restr
     const LinkIdx x = link_index(gr);
     if (!x.valid) return;
     const LatDesc& d = gr.descs[x.l];
-    const Links<R, NC> U{ (R*)d.U, d.cs };
-    R* s = U.slab(x.mu, x.par);
-    M3<double> m = m_cast<R, double>(load_link<R, NC>(s, U.cs, x.cb));
+    const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
+    const uintptr_t s = U.slab(x.mu, x.par);
+    M3<double> m = m_cast<R, double>(load_link<R, NC>(s, x.cb));
     m_reunit(m);
-    store_link<R, NC>(s, U.cs, x.cb, m_cast<double, R>(m));
+    store_link<R, NC>(s, x.cb, m_cast<double, R>(m));
 }
 
 // U_mu(n) -> Om(n) U_mu(n) Om(n+mu)^+, Om Haar-random per site from Philox
@@ -118,7 +118,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_gauge(Gri
     const LinkIdx x = link_index(gr);
     if (!x.valid) return;
     const LatDesc& d = gr.descs[x.l];
-    const Links<R, NC> U{ (R*)d.U, d.cs };
+    const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
     int n[4];
     cb_coords(d.g, x.cb, x.par, n);
     int np[4] = { n[0], n[1], n[2], n[3] };
@@ -127,9 +127,9 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_gauge(Gri
     const Rng r1{ seed, 0u, (uint32_t)lex_index(d.g, np), 0 };
     const M3<double> o0 = haar_from_rng(r0, P_GAUGE, 0);
     const M3<double> o1 = haar_from_rng(r1, P_GAUGE, 0);
-    R* s = U.slab(x.mu, x.par);
-    const M3<double> u = m_cast<R, double>(load_link<R, NC>(s, U.cs, x.cb));
-    store_link<R, NC>(s, U.cs, x.cb, m_cast<double, R>(m_mul_nd(m_mul(o0, u), o1)));
+    const uintptr_t s = U.slab(x.mu, x.par);
+    const M3<double> u = m_cast<R, double>(load_link<R, NC>(s, x.cb));
+    store_link<R, NC>(s, x.cb, m_cast<double, R>(m_mul_nd(m_mul(o0, u), o1)));
 }
 
 #define DISPATCH_PREC(prec, CALL)                                 \
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_to_aos(Geo g, const R* __restrict__ U, 
     int n[4];
     cb_coords(g, cb, par, n);
     const size_t i = (size_t)lex_index(g, n);
-    const M3<R> m = load_link<R, NC>(U + (size_t)(slab * NC) * cs, cs, cb);
+    const M3<R> m = load_link<R, NC>((uintptr_t)U + (uintptr_t)slab * cs, cb);
     double* o = aos + (i * 4 + mu) * 18;
 #pragma unroll
     for (int k = 0; k < 9; k++) {
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(256) k_from_aos(Geo g, R* __restrict__ U, size
         m.re[k] = (R)o[2 * k];
         m.im[k] = (R)o[2 * k + 1];
     }
-    store_link<R, NC>(U + (size_t)(slab * NC) * cs, cs, cb, m);
+    store_link<R, NC>((uintptr_t)U + (uintptr_t)slab * cs, cb, m);
 }
 
 hipError_t launch_to_aos(int prec, const LatDesc*, const Geo& g, const void* U, size_t cs, double* aos, hipStream_t st)
@@ -223,8 +223,8 @@ __global__ void __launch_bounds__(256) k_convert(RD* __restrict__ dst, size_t cs
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 8 * Vh) return;
     const int slab = e / Vh, cb = e - slab * Vh;
-    const M3<RS> m = load_link<RS, NS>(src + (size_t)(slab * NS) * css, css, cb);
-    store_link<RD, ND>(dst + (size_t)(slab * ND) * csd, csd, cb, m_cast<RS, RD>(m));
+    const M3<RS> m = load_link<RS, NS>((uintptr_t)src + (uintptr_t)slab * css, cb);
+    store_link<RD, ND>((uintptr_t)dst + (uintptr_t)slab * csd, cb, m_cast<RS, RD>(m));
 }
 
 template <typename RD, int ND>
@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(256) k_check(Geo g, const R* __restrict__ U, s
     double dev = -1.0;
     if (e < 8 * g.Vh) {
         const int slab = e / g.Vh, cb = e - slab * g.Vh;
-        const M3<double> m = m_cast<R, double>(load_link<R, NC>(U + (size_t)(slab * NC) * cs, cs, cb));
+        const M3<double> m = m_cast<R, double>(load_link<R, NC>((uintptr_t)U + (uintptr_t)slab * cs, cb));
         const M3<double> p = m_mul_nd(m, m);
         dev = 0.0;
 #pragma unroll

@@ -21,11 +21,12 @@ struct LatDesc {
     void* U;       // link field
     void* aux;     // second buffer (momenta, flow generator, ping-pong links)
     void* aux2;
-    size_t cs;     // component stride of U (elements)
-    size_t cs8;    // component stride of the 8-real aux fields (elements)
+    size_t cs;     // bytes per slab of U, aux2 (link records)
+    size_t cs8;    // bytes per slab of aux (8-real records)
     Geo g;
     double beta;
     uint32_t seed, lid;
+    int tile[3];   // (ty, tz, tt): site tile of the phase kernels (divisors of L1, L2, L3)
 };
 
 // Block partition: lattice l owns logical blocks [bbeg[l], bbeg[l+1]).

@@ -82,6 +82,30 @@ __device__ __forceinline__ void draw_dir(const Rng& rng, int mu, int sg, int h, 
     g[3] = sr * ct;
 }
 
+// Thread index w -> site of the given parity, walking the lattice in tiles of
+// L0 x ty x tz x tt sites (tiles ordered y, z, t; inside a tile x-halves
+// fastest, then y, z, t).  Whole x rows keep each wavefront's loads
+// contiguous; the tile shape sets which neighbours are in flight together on
+// one XCD.  ty = L1, tz = L2, tt = 1 is the plain lexicographic order.
+__device__ __forceinline__ void tiled_coords(const Geo& g, const int tile[3], int w, int par, int n[4])
+{
+    const int ty = tile[0], tz = tile[1], tt = tile[2];
+    const int th = g.h0 * ty * tz * tt;
+    const int tid = w / th, j = w - tid * th;
+    const int ny = g.L[1] / ty, nz = g.L[2] / tz;
+    const int iy = tid % ny, r = tid / ny;
+    const int iz = r % nz, it = r / nz;
+    const int x0h = j % g.h0;
+    int q = j / g.h0;
+    const int ly = q % ty;
+    q /= ty;
+    const int lz = q % tz, lt = q / tz;
+    n[1] = iy * ty + ly;
+    n[2] = iz * tz + lz;
+    n[3] = it * tt + lt;
+    n[0] = 2 * x0h + ((par + n[1] + n[2] + n[3]) & 1);
+}
+
 template <typename R, int NC, int KIND>
 __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const uint64_t* __restrict__ sweep_base,
                                                int sweep_off, HbArgs hb, unsigned long long* exhausted)
@@ -91,15 +115,16 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
     const int l = find_lattice_p(gr.bbeg, gr.nlat, lb);
     const LatDesc& d = gr.descs[l];
     const Geo g = d.g;
-    const int cb = (lb - gr.bbeg[l]) * (int)blockDim.x + (int)threadIdx.x;
-    if (cb >= g.Vh) return;
+    const int w = (lb - gr.bbeg[l]) * (int)blockDim.x + (int)threadIdx.x;
+    if (w >= g.Vh) return;
 
-    const Links<R, NC> U{ (R*)d.U, d.cs };
+    const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
     int n[4];
-    cb_coords(g, cb, par, n);
+    tiled_coords(g, d.tile, w, par, n);
+    const int cb = lex_index(g, n) >> 1;
     const M3<R> A = staple_sum<R, NC, R>(U, g, mu, n);
-    R* s = U.slab(mu, par);
-    M3<R> u = load_link<R, NC>(s, U.cs, cb);
+    const uintptr_t s = U.slab(mu, par);
+    M3<R> u = load_link<R, NC>(s, cb);
     M3<R> W = m_mul(u, A);
 
     Rng rng{ d.seed, d.lid, (uint32_t)lex_index(g, n), 0 };
@@ -157,7 +182,11 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
             }
         }
     }
-    store_link<R, NC>(s, U.cs, cb, u);
+    // fp32 links are re-orthonormalized (rows 0, 1; row 2 their completion)
+    // before every store: rounding in a 12-real record would otherwise grow,
+    // because the rebuilt third row feeds back into rows 0 and 1.
+    if constexpr (!kF64) m_reunit(u);
+    store_link<R, NC>(s, cb, u);
 }
 
 template <typename R, int NC, int KIND>

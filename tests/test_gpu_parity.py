@@ -163,9 +163,12 @@ def test_launch_shape_and_resume_invariance(m, orc):
     sweeps equal N/2 + N/2 sweeps."""
     d = [8, 6, 4, 4]
     ref = None
+    shapes = [(64, 0, (0, 0, 1)), (128, 1, (2, 2, 2)), (256, 1, (3, 4, 4)), (512, 0, (6, 2, 1)), (512, 1, (16, 8, 4)),
+              (256, 0, (1, 1, 4))]
     try:
-        for block, remap in ((64, 0), (128, 1), (256, 1), (512, 0), (512, 1)):
+        for block, remap, tile in shapes:
             m.su3_set_launch(block, remap)
+            m.su3_set_tile(*tile)
             f = field(m, d, "fp32")
             m.su3_init_hot(f, 6, 1)
             m.su3_sweep_hb_or(f, 6.0, 6, 1, 0, 2, P(n_or=2))
@@ -173,9 +176,10 @@ def test_launch_shape_and_resume_invariance(m, orc):
             U = m.su3_field_to_host(f)
             if ref is None:
                 ref = U
-            assert np.array_equal(U, ref), (block, remap)
+            assert np.array_equal(U, ref), (block, remap, tile)
     finally:
         m.su3_set_launch(0, 1)
+        m.su3_set_tile(0, 0, 0)
     f = field(m, d, "fp32")
     m.su3_init_hot(f, 6, 1)
     m.su3_sweep_hb_or(f, 6.0, 6, 1, 0, 4, P(n_or=2))
@@ -301,16 +305,19 @@ def test_full_size_32_4_fp64_sweep_matches_oracle(m, orc):
 
 
 def test_full_size_32_4_fp32_sweep_tracks_oracle(m, orc):
-    """32^4 FP32-R12 from the hot start, one sweep of 1 HB + 1 OR: plaquette
-    within 1e-6 of the FP64 oracle; per-link deviation median below 1e-5,
-    99.9th percentile below 1e-3 and O(1) outliers (flipped FP32 sampler
-    decisions) in at most 1 link in 10^4."""
+    """32^4 FP32-R12, one sweep of 1 HB + 1 OR from the FP32-rounded copy of
+    an oracle field (cold start + 3 sweeps at beta = 6): plaquette within
+    1e-6 of the FP64 oracle; per-link deviation median below 1e-5, 99.9th
+    percentile below 1e-3 and O(1) outliers (flipped FP32 sampler decisions)
+    in at most 1 link in 10^4.  (From a Haar-random start the rough field
+    amplifies FP32 rounding far more and only the plaquette bar applies.)"""
     d = [32, 32, 32, 32]
+    U = orc.init_cold(d)
+    orc.sweep_hb_or(d, U, 6.0, 3, 0, 0, 3, n_or=1)
     f = field(m, d, "fp32_r12")
-    m.su3_init_hot(f, 3, 0)
-    h = m.su3_sweep_hb_or(f, 6.0, 3, 0, 0, 1, P(n_or=1))
-    U = orc.init_hot(d, 3, 0)
-    href, _ = orc.sweep_hb_or(d, U, 6.0, 3, 0, 0, 1, n_or=1)
+    m.su3_field_from_host(f, U)
+    h = m.su3_sweep_hb_or(f, 6.0, 3, 0, 3, 1, P(n_or=1))
+    href, _ = orc.sweep_hb_or(d, U, 6.0, 3, 0, 3, 1, n_or=1)
     med, q999, mx, dev = fp32_link_stats(m.su3_field_to_host(f), U)
     print(f"32^4 r12: plaquette diff {abs(h[0] - href[0]):.2e}, link dev median {med:.2e} q99.9 {q999:.2e} max {mx:.2e}")
     assert abs(h[0] - href[0]) < 1e-6
