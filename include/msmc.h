@@ -124,7 +124,7 @@ int32_t su3_restrict(su3_field fine, su3_field coarse);
  * until the partial action S_d changes by at most rel_tol relative to the
  * previous step, or max_iter steps.  The interpolation runs in fp64; the
  * result is rounded into fine's precision.  Paper values: c = 0.05,
- * rel_tol = 1e-5 (Sec. IV.B/C).  iters_out (3 ints, may be NULL) receives
+ * rel_tol = 1e-5 (Sec. IV.C).  iters_out (3 ints, may be NULL) receives
  * the steps taken per stage. */
 int32_t su3_prolongate(su3_field coarse, su3_field fine, double c, double rel_tol, int32_t max_iter,
                        int32_t iters_out[3]);
@@ -148,7 +148,7 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
                               const uint32_t* lattice_ids, uint64_t first_sweep, int32_t n_sweeps,
                               const su3_hb_params* p, double* plaq_out);
 
-/* One HMC trajectory (Sec. IV.C, App. A): momenta p^a ~ N(0,1) from Philox
+/* One HMC trajectory (Sec. IV.E, App. A): momenta p^a ~ N(0,1) from Philox
  * purpose MOM with the 64-bit trajectory index traj; H = (1/2) sum p^2 + S in
  * fp64; kick-drift-kick leapfrog with eps = tau / n_steps, U <- exp(i eps P)
  * U, in the storage precision; Metropolis with the uniform of Philox purpose

@@ -680,7 +680,7 @@ int64_t orc_sweep_hb_or(const int32_t L[4], double* U, double beta, uint32_t see
 }
 
 /* ------------------------------------------------------------------ */
-/* HMC (Sec. IV.C and App. A): PQP leapfrog, unit trajectories.         */
+/* HMC (Sec. IV.E and App. A): PQP leapfrog, unit trajectories.         */
 /* Momenta p^a (a = 1..8) per link, P = sum_a p^a T^a, T^a = lambda^a/2, */
 /* H = (1/2) sum p^a p^a + S(U), dU/dtau = i P U.                       */
 /* ------------------------------------------------------------------ */
@@ -1053,7 +1053,7 @@ void orc_wilson_flow(const int32_t L[4], double* U, double eps, int32_t n_steps)
 }
 
 /* ------------------------------------------------------------------ */
-/* Clover field strength and topological charge (Sec. IV.C uses an      */
+/* Clover field strength and topological charge (Sec. IV.D uses an      */
 /* improved definition; this is the clover one).                        */
 /* Q_munu(x) = sum of the four counter-clockwise leaves in the munu     */
 /* plane at x; F_munu = traceless part of (Q_munu - Q_munu^+)/8;        */

@@ -1,5 +1,5 @@
 // k_hmc.hip -- HMC momentum refresh, fused kick-drift leapfrog step and the
-// kinetic-energy reduction (Sec. IV.C, App. A).
+// kinetic-energy reduction (Sec. IV.E, App. A).
 //
 // Momenta: p^a, a = 1..8, per link, P = sum_a p^a lambda^a / 2, stored as 8
 // reals per link in the same structure-of-arrays scheme as the links:

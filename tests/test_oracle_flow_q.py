@@ -1,5 +1,5 @@
 """Oracle pins for the Wilson flow (Sec. IV.B) and the clover topological
-charge (Sec. IV.C; clover reading of the charge density)."""
+charge (Sec. IV.D; clover reading of the charge density)."""
 import numpy as np
 import pytest
 from scipy.linalg import expm

@@ -1,4 +1,4 @@
-"""Oracle pins for HMC (Sec. IV.C, App. A): force = derivative of the
+"""Oracle pins for HMC (Sec. IV.E, App. A): force = derivative of the
 Wilson action, leapfrog error scaling, reversibility, Creutz equality."""
 import numpy as np
 import pytest
