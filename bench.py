@@ -85,6 +85,34 @@ def run_variant(m, torch, prec, n_lat, dims, steps, warmup, beta=6.0, n_or=4):
     return out
 
 
+def run_hmc(m, torch, dims, n_traj=20, n_steps=40, beta=6.0, therm=200, prec="fp32"):
+    """HMC on one lattice: cold start + `therm` HB+OR sweeps at beta (seed 5),
+    then n_traj unit trajectories of n_steps leapfrog steps (fp32 molecular
+    dynamics, fp64 Hamiltonian and Metropolis test)."""
+    f = m.Field(dims, prec)
+    m.su3_init_cold(f)
+    m.su3_sweep_hb_or(f, beta, 5, 0, 0, therm, m.hb_params(n_or=4, reunit_every=10), record=False)
+    m.su3_hmc_trajectory(f, beta, 1.0, n_steps, 5, 0, 10**6, 1)  # warm-up (allocates scratch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dh, acc = [], 0
+    for t in range(n_traj):
+        a, d = m.su3_hmc_trajectory(f, beta, 1.0, n_steps, 5, 0, t, 1)
+        acc += a
+        dh.append(d)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    import math
+    out = {"lattice": f"{dims[0]}^4", "beta": beta, "tau": 1.0, "n_steps": n_steps, "trajectories": n_traj,
+           "precision": f"{prec} molecular dynamics, fp64 Hamiltonian", "trajectories_per_s": round(n_traj / wall, 3),
+           "ms_per_trajectory": round(1e3 * wall / n_traj, 3), "acceptance": acc / n_traj,
+           "mean_dH": round(sum(dh) / n_traj, 5), "mean_exp_minus_dH": round(sum(math.exp(-x) for x in dh) / n_traj, 5),
+           "plaquette": round(m.su3_plaquette(f), 8),
+           "start": f"cold + {therm} HB+OR sweeps at beta {beta}"}
+    f.close()
+    return out
+
+
 def roofline(v):
     per_launch = v["phase_links"] * PHASE_RECORDS * LINK_BYTES[v["prec"]]
     achieved = per_launch / (v["or_kernel_us"] * 1e-6) / 1e9
@@ -133,6 +161,7 @@ def main():
     ap.add_argument("--only", default="", help="comma list of variants to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--no-hmc", action="store_true", help="skip the HMC report")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -162,6 +191,11 @@ def main():
         log(f"bench: {name}: {res[name]['updates_per_s']:.3e} link updates/s, "
             f"OR kernel {res[name]['or_kernel_us']:.1f} us, HB kernel {res[name]['hb_kernel_us']:.1f} us")
     head = res.get("r12_batch") or next(iter(res.values()))
+    hmc = None
+    if not a.no_hmc and not a.only:
+        log("bench: hmc (32^4, tau 1, 40 steps, 20 trajectories) ...")
+        hmc = run_hmc(m, torch, dims)
+        log(f"bench: hmc {hmc['trajectories_per_s']} traj/s, acceptance {hmc['acceptance']}")
     cpu = None
     if not a.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
@@ -192,6 +226,8 @@ def main():
                          "launch": v["launch"]}
                      for k, v in res.items()},
     }
+    if hmc is not None:
+        line["hmc"] = hmc
     if "fp64" in res:
         line["fp64_single_link_updates_per_s"] = round(res["fp64"]["updates_per_s"], 1)
         line["speedup_fp32_batched_vs_fp64"] = round(head["updates_per_s"] / res["fp64"]["updates_per_s"], 3)

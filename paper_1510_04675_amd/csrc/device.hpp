@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace msmc {
 
 // ---------------------------------------------------------------------------
@@ -227,86 +229,54 @@ template <typename R> __device__ __forceinline__ void m_set_one(M3<R>& a)
     a.re[0] = a.re[4] = a.re[8] = R(1);
 }
 
-// C = A B
-template <typename R> __device__ __forceinline__ M3<R> m_mul(const M3<R>& a, const M3<R>& b)
+// 3x3 complex products with either factor optionally daggered.
+// fp64: each complex product is formed as (ac - bd, ad + bc) and added to
+// the running sum in k order, with no contraction -- the order the fp64 chain
+// is specified in.  fp32: the same sums as chains of fused multiply-adds
+// (four per complex multiply-accumulate).
+template <bool DA, bool DB, typename R>
+__device__ __forceinline__ void mm_acc(M3<R>& c, const M3<R>& a, const M3<R>& b)
 {
-    M3<R> c;
 #pragma unroll
     for (int r = 0; r < 3; r++)
 #pragma unroll
         for (int s = 0; s < 3; s++) {
-            R xr = R(0), xi = R(0);
+            R xr = c.re[r * 3 + s], xi = c.im[r * 3 + s];
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-                xr += a.re[r * 3 + k] * b.re[k * 3 + s] - a.im[r * 3 + k] * b.im[k * 3 + s];
-                xi += a.re[r * 3 + k] * b.im[k * 3 + s] + a.im[r * 3 + k] * b.re[k * 3 + s];
+                const R ar = DA ? a.re[k * 3 + r] : a.re[r * 3 + k];
+                const R ai = DA ? -a.im[k * 3 + r] : a.im[r * 3 + k];
+                const R br = DB ? b.re[s * 3 + k] : b.re[k * 3 + s];
+                const R bi = DB ? -b.im[s * 3 + k] : b.im[k * 3 + s];
+                if constexpr (std::is_same<R, float>::value) {
+                    xr = fmaf(ar, br, xr);
+                    xr = fmaf(-ai, bi, xr);
+                    xi = fmaf(ar, bi, xi);
+                    xi = fmaf(ai, br, xi);
+                } else {
+                    xr += ar * br - ai * bi;
+                    xi += ar * bi + ai * br;
+                }
             }
             c.re[r * 3 + s] = xr;
             c.im[r * 3 + s] = xi;
         }
+}
+
+template <bool DA, bool DB, typename R> __device__ __forceinline__ M3<R> mm(const M3<R>& a, const M3<R>& b)
+{
+    M3<R> c;
+#pragma unroll
+    for (int k = 0; k < 9; k++) c.re[k] = c.im[k] = R(0);
+    mm_acc<DA, DB>(c, a, b);
     return c;
 }
 
-// C = A B^+
-template <typename R> __device__ __forceinline__ M3<R> m_mul_nd(const M3<R>& a, const M3<R>& b)
-{
-    M3<R> c;
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int s = 0; s < 3; s++) {
-            R xr = R(0), xi = R(0);
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                xr += a.re[r * 3 + k] * b.re[s * 3 + k] + a.im[r * 3 + k] * b.im[s * 3 + k];
-                xi += a.im[r * 3 + k] * b.re[s * 3 + k] - a.re[r * 3 + k] * b.im[s * 3 + k];
-            }
-            c.re[r * 3 + s] = xr;
-            c.im[r * 3 + s] = xi;
-        }
-    return c;
-}
-
-// C = A^+ B
-template <typename R> __device__ __forceinline__ M3<R> m_mul_dn(const M3<R>& a, const M3<R>& b)
-{
-    M3<R> c;
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int s = 0; s < 3; s++) {
-            R xr = R(0), xi = R(0);
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                xr += a.re[k * 3 + r] * b.re[k * 3 + s] + a.im[k * 3 + r] * b.im[k * 3 + s];
-                xi += a.re[k * 3 + r] * b.im[k * 3 + s] - a.im[k * 3 + r] * b.re[k * 3 + s];
-            }
-            c.re[r * 3 + s] = xr;
-            c.im[r * 3 + s] = xi;
-        }
-    return c;
-}
-
-// C = A^+ B^+
-template <typename R> __device__ __forceinline__ M3<R> m_mul_dd(const M3<R>& a, const M3<R>& b)
-{
-    M3<R> c;
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int s = 0; s < 3; s++) {
-            R xr = R(0), xi = R(0);
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                // conj(a[k][r]) * conj(b[s][k])
-                xr += a.re[k * 3 + r] * b.re[s * 3 + k] - a.im[k * 3 + r] * b.im[s * 3 + k];
-                xi -= a.re[k * 3 + r] * b.im[s * 3 + k] + a.im[k * 3 + r] * b.re[s * 3 + k];
-            }
-            c.re[r * 3 + s] = xr;
-            c.im[r * 3 + s] = xi;
-        }
-    return c;
-}
+// C = A B, A B^+, A^+ B, A^+ B^+
+template <typename R> __device__ __forceinline__ M3<R> m_mul(const M3<R>& a, const M3<R>& b) { return mm<false, false>(a, b); }
+template <typename R> __device__ __forceinline__ M3<R> m_mul_nd(const M3<R>& a, const M3<R>& b) { return mm<false, true>(a, b); }
+template <typename R> __device__ __forceinline__ M3<R> m_mul_dn(const M3<R>& a, const M3<R>& b) { return mm<true, false>(a, b); }
+template <typename R> __device__ __forceinline__ M3<R> m_mul_dd(const M3<R>& a, const M3<R>& b) { return mm<true, true>(a, b); }
 
 template <typename R> __device__ __forceinline__ void m_acc(M3<R>& a, const M3<R>& b)
 {
@@ -349,10 +319,23 @@ template <typename R> __device__ __forceinline__ void m_complete_row2(M3<R>& a)
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-        R xr = a.re[c1] * a.re[3 + c2] - a.im[c1] * a.im[3 + c2] - (a.re[c2] * a.re[3 + c1] - a.im[c2] * a.im[3 + c1]);
-        R xi = a.re[c1] * a.im[3 + c2] + a.im[c1] * a.re[3 + c2] - (a.re[c2] * a.im[3 + c1] + a.im[c2] * a.re[3 + c1]);
-        a.re[6 + c] = xr;
-        a.im[6 + c] = -xi;
+        if constexpr (std::is_same<R, float>::value) {
+            R xr = a.re[c1] * a.re[3 + c2];
+            xr = fmaf(-a.im[c1], a.im[3 + c2], xr);
+            xr = fmaf(-a.re[c2], a.re[3 + c1], xr);
+            xr = fmaf(a.im[c2], a.im[3 + c1], xr);
+            R ni = -(a.re[c1] * a.im[3 + c2]);
+            ni = fmaf(-a.im[c1], a.re[3 + c2], ni);
+            ni = fmaf(a.re[c2], a.im[3 + c1], ni);
+            ni = fmaf(a.im[c2], a.re[3 + c1], ni);
+            a.re[6 + c] = xr;
+            a.im[6 + c] = ni;
+        } else {
+            R xr = a.re[c1] * a.re[3 + c2] - a.im[c1] * a.im[3 + c2] - (a.re[c2] * a.re[3 + c1] - a.im[c2] * a.im[3 + c1]);
+            R xi = a.re[c1] * a.im[3 + c2] + a.im[c1] * a.re[3 + c2] - (a.re[c2] * a.im[3 + c1] + a.im[c2] * a.re[3 + c1]);
+            a.re[6 + c] = xr;
+            a.im[6 + c] = -xi;
+        }
     }
 }
 
@@ -645,13 +628,19 @@ __device__ __forceinline__ M3<C> staple_sum(const Links<R, NC>& U, const Geo& g,
             M3<C> a = m_cast<R, C>(load_at(U, g, nu, npm));
             M3<C> b = m_cast<R, C>(load_at(U, g, mu, npn));
             M3<C> c = m_cast<R, C>(load_at(U, g, nu, n));
-            m_acc(A, m_mul_nd(m_mul_nd(a, b), c));
+            if constexpr (std::is_same<C, float>::value)
+                mm_acc<false, true>(A, m_mul_nd(a, b), c);
+            else
+                m_acc(A, m_mul_nd(m_mul_nd(a, b), c));
         }
         {
             M3<C> a = m_cast<R, C>(load_at(U, g, nu, npm_mn));
             M3<C> b = m_cast<R, C>(load_at(U, g, mu, nmn));
             M3<C> c = m_cast<R, C>(load_at(U, g, nu, nmn));
-            m_acc(A, m_mul(m_mul_dd(a, b), c));
+            if constexpr (std::is_same<C, float>::value)
+                mm_acc<false, false>(A, m_mul_dd(a, b), c);
+            else
+                m_acc(A, m_mul(m_mul_dd(a, b), c));
         }
     }
     return A;
