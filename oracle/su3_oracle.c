@@ -419,25 +419,45 @@ static mat3 plaq_mat(const geom* g, const double* U, int64_t i, int mu, int nu)
 }
 
 /* Average plaquette: (1/(6V)) sum_n sum_{mu<nu} (1/3) Re Tr U_munu(n). */
+/* Compensated (Neumaier) summation.  Plaquette, action and kinetic energy
+ * add up 10^6 - 10^8 terms, and the Metropolis test needs the difference of
+ * two such sums: plain accumulation would lose about sqrt(n) ulps of the
+ * total, a compensated sum keeps the error near one ulp. */
+typedef struct {
+    double s, c;
+} ksum;
+
+static void ks_add(ksum* k, double x)
+{
+    double t = k->s + x;
+    if (fabs(k->s) >= fabs(x))
+        k->c += (k->s - t) + x;
+    else
+        k->c += (x - t) + k->s;
+    k->s = t;
+}
+
+static double ks_val(const ksum* k) { return k->s + k->c; }
+
 double orc_plaquette(const int32_t L[4], const double* U)
 {
     geom g = mkgeom(L);
-    double s = 0;
+    ksum s = { 0, 0 };
     for (int64_t i = 0; i < g.V; i++)
         for (int mu = 0; mu < 4; mu++)
-            for (int nu = mu + 1; nu < 4; nu++) s += creal(m_tr(plaq_mat(&g, U, i, mu, nu))) / 3.0;
-    return s / (6.0 * (double)g.V);
+            for (int nu = mu + 1; nu < 4; nu++) ks_add(&s, creal(m_tr(plaq_mat(&g, U, i, mu, nu))) / 3.0);
+    return ks_val(&s) / (6.0 * (double)g.V);
 }
 
 /* Wilson action S = beta sum_n sum_{mu<nu} [1 - (1/3) Re Tr U_munu(n)]. */
 double orc_action(const int32_t L[4], const double* U, double beta)
 {
     geom g = mkgeom(L);
-    double s = 0;
+    ksum s = { 0, 0 };
     for (int64_t i = 0; i < g.V; i++)
         for (int mu = 0; mu < 4; mu++)
-            for (int nu = mu + 1; nu < 4; nu++) s += 1.0 - creal(m_tr(plaq_mat(&g, U, i, mu, nu))) / 3.0;
-    return beta * s;
+            for (int nu = mu + 1; nu < 4; nu++) ks_add(&s, 1.0 - creal(m_tr(plaq_mat(&g, U, i, mu, nu))) / 3.0);
+    return beta * ks_val(&s);
 }
 
 /* Staple sum A_mu(n): for nu != mu ascending, the forward term
@@ -701,6 +721,7 @@ void orc_hmc_momenta(const int32_t L[4], double* p, uint32_t seed, uint32_t lid,
 void orc_hmc_force(const int32_t L[4], const double* U, double beta, double* F)
 {
     geom g = mkgeom(L);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < g.V; i++)
         for (int mu = 0; mu < 4; mu++) {
             mat3 Om = m_mul(ld(U, i, mu), staple(&g, U, i, mu));
@@ -714,14 +735,15 @@ void orc_hmc_force(const int32_t L[4], const double* U, double beta, double* F)
 double orc_hmc_kinetic(const int32_t L[4], const double* p)
 {
     geom g = mkgeom(L);
-    double k = 0;
-    for (int64_t j = 0; j < g.V * 4 * 8; j++) k += 0.5 * p[j] * p[j];
-    return k;
+    ksum k = { 0, 0 };
+    for (int64_t j = 0; j < g.V * 4 * 8; j++) ks_add(&k, 0.5 * p[j] * p[j]);
+    return ks_val(&k);
 }
 
 /* U <- exp(i eps P) U for every link. */
 static void drift(const geom* g, double* U, const double* p, double eps)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < g->V; i++)
         for (int mu = 0; mu < 4; mu++) {
             mat3 P = m_zero();
@@ -835,14 +857,20 @@ void orc_prolong_transfer(const int32_t Lc[4], const double* Uc, double* Uf)
 double orc_partial_action(const int32_t L[4], const double* U, int32_t d, double beta)
 {
     geom g = mkgeom(L);
-    double s = 0;
+    /* the six plane terms of every site (in parallel; 0 where chi_munu != d),
+     * then summed in site and plane order */
+    double* term = (double*)malloc(sizeof(double) * (size_t)g.V * 6);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < g.V; i++) {
-        int n[4];
+        int n[4], k = 0;
         coords(&g, i, n);
         for (int mu = 0; mu < 4; mu++)
-            for (int nu = mu + 1; nu < 4; nu++)
-                if (chi_excl(n, mu, nu) == d) s += 1.0 - creal(m_tr(plaq_mat(&g, U, i, mu, nu))) / 3.0;
+            for (int nu = mu + 1; nu < 4; nu++, k++)
+                term[i * 6 + k] = (chi_excl(n, mu, nu) == d) ? 1.0 - creal(m_tr(plaq_mat(&g, U, i, mu, nu))) / 3.0 : 0.0;
     }
+    double s = 0;
+    for (int64_t j = 0; j < g.V * 6; j++) s += term[j];
+    free(term);
     return beta * s;
 }
 
@@ -892,6 +920,7 @@ void orc_ape_step(const int32_t L[4], double* U, int32_t d, double c)
     size_t nU = (size_t)g.V * 72;
     double* Uold = (double*)malloc(sizeof(double) * nU);
     memcpy(Uold, U, sizeof(double) * nU);
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < g.V; i++) {
         int n[4];
         coords(&g, i, n);
@@ -1014,6 +1043,7 @@ static mat3 flow_generator(mat3 Om)
 
 static void flow_Z(const geom* g, const double* U, mat3* Z, double eps)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < g->V; i++)
         for (int mu = 0; mu < 4; mu++)
             Z[i * 4 + mu] = m_scale(flow_generator(m_mul(ld(U, i, mu), staple(g, U, i, mu))), eps);
@@ -1030,17 +1060,20 @@ void orc_wilson_flow(const int32_t L[4], double* U, double eps, int32_t n_steps)
     mat3* Z2 = (mat3*)malloc(sizeof(mat3) * nl);
     for (int32_t s = 0; s < n_steps; s++) {
         flow_Z(&g, U, Z0, eps);
+#pragma omp parallel for schedule(static)
         for (size_t l = 0; l < nl; l++) {
             mat3 m = m_mul(m_exp(m_scale(Z0[l], 0.25)), ld(U, (int64_t)(l / 4), (int)(l % 4)));
             st(U, (int64_t)(l / 4), (int)(l % 4), &m);
         }
         flow_Z(&g, U, Z1, eps);
+#pragma omp parallel for schedule(static)
         for (size_t l = 0; l < nl; l++) {
             mat3 X = m_sub(m_scale(Z1[l], 8.0 / 9.0), m_scale(Z0[l], 17.0 / 36.0));
             mat3 m = m_mul(m_exp(X), ld(U, (int64_t)(l / 4), (int)(l % 4)));
             st(U, (int64_t)(l / 4), (int)(l % 4), &m);
         }
         flow_Z(&g, U, Z2, eps);
+#pragma omp parallel for schedule(static)
         for (size_t l = 0; l < nl; l++) {
             mat3 X = m_add(m_sub(m_scale(Z2[l], 0.75), m_scale(Z1[l], 8.0 / 9.0)), m_scale(Z0[l], 17.0 / 36.0));
             mat3 m = m_mul(m_exp(X), ld(U, (int64_t)(l / 4), (int)(l % 4)));
