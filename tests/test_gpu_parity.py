@@ -74,6 +74,24 @@ def test_plaquette_action_charge_energy_match_oracle(m, orc):
     assert abs(m.su3_clover_energy(f) - orc.clover_energy(d, U)) < 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp32_r12"])
+def test_reduced_precision_plaquette_of_the_same_field(m, orc, prec):
+    """Measurement parity: the plaquette of an FP32 / FP32-R12 field (R12
+    uses the SU(3) row identity in fp32 per plaquette, summed in fp64)
+    against the oracle's FP64 plaquette of exactly the stored links, to 1e-7;
+    ragged extents and several blocks."""
+    d = [10, 6, 4, 6]
+    U = si.random_field(d, 12)
+    orc.wilson_flow(d, U, 0.02, 2)
+    f = field(m, d, prec)
+    m.su3_field_from_host(f, U)
+    Uh = m.su3_field_to_host(f)
+    p = m.su3_plaquette(f)
+    pref = orc.plaquette(d, Uh)
+    print(f"{prec}: plaquette {p:.12f} oracle {pref:.12f}")
+    assert abs(p - pref) < 1e-7
+
+
 def test_gauge_transform_matches_oracle(m, orc):
     d = [4, 4, 2, 4]
     U = si.random_field(d, 8)
