@@ -45,8 +45,11 @@ def run_variant(m, torch, prec, n_lat, dims, steps, warmup, beta=6.0, n_or=4):
     seeds = [3] * n_lat
     lids = list(range(n_lat))
     sweep = 0
+    plaq_first = None
     for _ in range(warmup):
-        m.su3_batch_sweep_hb_or(fields, betas, seeds, lids, sweep, 1, params)
+        pw = m.su3_batch_sweep_hb_or(fields, betas, seeds, lids, sweep, 1, params)
+        if plaq_first is None:
+            plaq_first = float(pw[0, 0])
         sweep += 1
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -69,6 +72,7 @@ def run_variant(m, torch, prec, n_lat, dims, steps, warmup, beta=6.0, n_or=4):
     torch.cuda.synchronize()
     hb_ms, hb_n = m.su3_profile_read(0)
     or_ms, or_n = m.su3_profile_read(1)
+    pl_ms, pl_n = m.su3_profile_read(2)
     m.su3_profile_enable(False)
     V = dims[0] * dims[1] * dims[2] * dims[3]
     updates = 5 * 4 * V * n_lat * steps if n_or == 4 else (1 + n_or) * 4 * V * n_lat * steps
@@ -77,8 +81,11 @@ def run_variant(m, torch, prec, n_lat, dims, steps, warmup, beta=6.0, n_or=4):
         "prec": prec, "n_lat": n_lat, "launch": cfg, "wall_s": wall, "event_ms": ev_ms,
         "ms_per_step": wall * 1e3 / steps, "updates_per_s": updates / wall,
         "hb_kernel_us": 1e3 * hb_ms / max(hb_n, 1), "or_kernel_us": 1e3 * or_ms / max(or_n, 1),
+        "plaq_kernel_us": 1e3 * pl_ms / max(pl_n, 1),
         "hb_launches": hb_n, "or_launches": or_n, "plaq_last": float(plaq[-1].mean()),
-        "phase_links": V // 2 * n_lat,
+        "phase_links": V // 2 * n_lat, "plaq_first": plaq_first,
+        "sweeps_per_s": n_lat * steps / wall,
+        "hb_updates_per_s": (V // 2 * n_lat) / (1e-3 * hb_ms / max(hb_n, 1)),
     }
     for f in fields:
         f.close()
@@ -92,7 +99,15 @@ def run_hmc(m, torch, dims, n_traj=20, n_steps=40, beta=6.0, therm=200, prec="fp
     f = m.Field(dims, prec)
     m.su3_init_cold(f)
     m.su3_sweep_hb_or(f, beta, 5, 0, 0, therm, m.hb_params(n_or=4, reunit_every=10), record=False)
-    m.su3_hmc_trajectory(f, beta, 1.0, n_steps, 5, 0, 10**6, 1)  # warm-up (allocates scratch)
+    # deviation from fp64: one trajectory of the same start in both precisions
+    a32, a64 = m.Field(dims, prec), m.Field(dims, "fp64")
+    m.su3_field_copy(a32, f)
+    m.su3_field_copy(a64, f)
+    _, dh32 = m.su3_hmc_trajectory(a32, beta, 1.0, n_steps, 5, 0, 10**6, 0)
+    _, dh64 = m.su3_hmc_trajectory(a64, beta, 1.0, n_steps, 5, 0, 10**6, 0)
+    a32.close()
+    a64.close()
+    m.su3_hmc_trajectory(f, beta, 1.0, n_steps, 5, 0, 10**6 + 1, 1)  # warm-up (allocates the field's scratch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dh, acc = [], 0
@@ -108,6 +123,7 @@ def run_hmc(m, torch, dims, n_traj=20, n_steps=40, beta=6.0, therm=200, prec="fp
            "ms_per_trajectory": round(1e3 * wall / n_traj, 3), "acceptance": acc / n_traj,
            "mean_dH": round(sum(dh) / n_traj, 5), "mean_exp_minus_dH": round(sum(math.exp(-x) for x in dh) / n_traj, 5),
            "plaquette": round(m.su3_plaquette(f), 8),
+           "dH_same_start": {prec: dh32, "fp64": dh64, "abs_dev": abs(dh32 - dh64)},
            "start": f"cold + {therm} HB+OR sweeps at beta {beta}"}
     f.close()
     return out
@@ -162,6 +178,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-hmc", action="store_true", help="skip the HMC report")
+    ap.add_argument("--launch", default="", help="fix the launch shape block,xcd_remap,ty,tz,tt (implies --no-tune)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -178,7 +195,11 @@ def main():
         return
     L = a.lattice
     dims = [L, L, L, L]
-    m.su3_autotune(not a.no_tune)
+    if a.launch:
+        b, r, ty, tz, tt = (int(x) for x in a.launch.split(","))
+        m.su3_set_launch(b, r)
+        m.su3_set_tile(ty, tz, tt)
+    m.su3_autotune(not (a.no_tune or a.launch))
     want = set(a.only.split(",")) if a.only else {"fp64", "fp32", "fp32_r12", "fp32_batch", "r12_batch"}
     res = {}
     plan = [("fp64", "fp64", 1), ("fp32", "fp32", 1), ("fp32_r12", "fp32_r12", 1),
@@ -189,7 +210,8 @@ def main():
         log(f"bench: {name} ({n} x {L}^4) ...")
         res[name] = run_variant(m, torch, prec, n, dims, a.steps, a.warmup)
         log(f"bench: {name}: {res[name]['updates_per_s']:.3e} link updates/s, "
-            f"OR kernel {res[name]['or_kernel_us']:.1f} us, HB kernel {res[name]['hb_kernel_us']:.1f} us")
+            f"OR kernel {res[name]['or_kernel_us']:.1f} us, HB kernel {res[name]['hb_kernel_us']:.1f} us, "
+            f"plaquette kernel {res[name]['plaq_kernel_us']:.1f} us")
     head = res.get("r12_batch") or next(iter(res.values()))
     hmc = None
     if not a.no_hmc and not a.only:
@@ -222,6 +244,10 @@ def main():
         "cpu_baseline": cpu,
         "variants": {k: {"link_updates_per_s": round(v["updates_per_s"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                          "or_kernel_us": round(v["or_kernel_us"], 2), "hb_kernel_us": round(v["hb_kernel_us"], 2),
+                         "plaq_kernel_us": round(v["plaq_kernel_us"], 2),
+                         "sweeps_per_s": round(v["sweeps_per_s"], 2),
+                         "hb_kernel_link_updates_per_s": round(v["hb_updates_per_s"], 1),
+                         "first_sweep_plaquette_lattice0": v["plaq_first"],
                          "or_hbm_frac": roofline(v)["frac"], "plaq_after": round(v["plaq_last"], 8),
                          "launch": v["launch"]}
                      for k, v in res.items()},
@@ -229,6 +255,11 @@ def main():
     if hmc is not None:
         line["hmc"] = hmc
     if "fp64" in res:
+        # every variant's lattice 0 starts from the same hot start and draws the
+        # same uniforms, so its first sweep is comparable with the fp64 one
+        p64 = res["fp64"]["plaq_first"]
+        line["first_sweep_plaquette_dev_vs_fp64"] = {k: abs(v["plaq_first"] - p64) for k, v in res.items()
+                                                      if k != "fp64" and p64 is not None and v["plaq_first"] is not None}
         line["fp64_single_link_updates_per_s"] = round(res["fp64"]["updates_per_s"], 1)
         line["speedup_fp32_batched_vs_fp64"] = round(head["updates_per_s"] / res["fp64"]["updates_per_s"], 3)
     print(json.dumps(line), flush=True)

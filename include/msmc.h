@@ -213,7 +213,8 @@ int32_t su3_get_config(const su3_field* fs, int32_t n, int32_t out[5]);
 /* Kernel timing with HIP events recorded on the field's stream around each
  * phase launch.  While enabled, su3_batch_sweep_hb_or launches the same
  * kernels eagerly instead of replaying its graph.  kind 0 = heat-bath
- * phases, 1 = overrelaxation phases.  Enabling resets the accumulators. */
+ * phases, 1 = overrelaxation phases, 2 = the per-sweep plaquette kernel.
+ * Enabling resets the accumulators. */
 int32_t su3_profile_enable(int32_t enable);
 int32_t su3_profile_read(int32_t kind, double* total_ms, int64_t* launches);
 

@@ -184,7 +184,7 @@ struct Plan {
     }
     Grid grid_site(const LatDesc* descs = nullptr) const
     {
-        return Grid{ descs ? descs : d_descs, d_bbeg_site, nlat, nblk_site, 256, 0 };
+        return Grid{ descs ? descs : d_descs, d_bbeg_site, nlat, nblk_site, 256, 1 };
     }
 };
 
@@ -254,6 +254,9 @@ static LatDesc base_desc(const su3_field_s* f)
     d.cs = f->cs;
     d.cs8 = f->cs8;
     d.g = f->geo();
+    d.mtile[0] = largest_divisor_upto(f->L[1], 8);
+    d.mtile[1] = largest_divisor_upto(f->L[2], 8);
+    d.mtile[2] = largest_divisor_upto(f->L[3], 4);
     return d;
 }
 
@@ -320,8 +323,8 @@ static bool g_tile_forced = false;
 static bool g_autotune = false;
 static std::map<std::string, LaunchCfg> g_tuned;
 static bool g_profile = false;
-static double g_prof_ms[2] = { 0, 0 };
-static long long g_prof_n[2] = { 0, 0 };
+static double g_prof_ms[3] = { 0, 0, 0 };
+static long long g_prof_n[3] = { 0, 0, 0 };
 static std::vector<hipEvent_t> g_events;
 
 static std::string shape_key(const std::vector<su3_field_s*>& fs)
@@ -408,7 +411,18 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
         }
         if (o.reunit_every > 0) HIPCHK(launch_reunit(p.prec, p.grid_link(), p.d_sweep, k, o.reunit_every, st));
         if (o.record) {
+            int ev = -1;
+            if (prof_marks) {
+                ev = (int)prof_marks->size() * 2;
+                int32_t rc = ensure_events((size_t)ev + 2);
+                if (rc) return rc;
+                HIPCHK(hipEventRecord(g_events[ev], st));
+            }
             HIPCHK(launch_plaq_partial(p.prec, p.grid_site(), p.d_partials, st));
+            if (prof_marks) {
+                HIPCHK(hipEventRecord(g_events[ev + 1], st));
+                prof_marks->push_back({ ev, 2 });
+            }
             HIPCHK(launch_reduce_final(p.grid_site(), p.d_partials, p.d_out, 1, k * p.nlat, st));
         }
     }
@@ -1331,14 +1345,14 @@ int32_t su3_profile_enable(int32_t enable)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     g_profile = enable != 0;
-    g_prof_ms[0] = g_prof_ms[1] = 0;
-    g_prof_n[0] = g_prof_n[1] = 0;
+    g_prof_ms[0] = g_prof_ms[1] = g_prof_ms[2] = 0;
+    g_prof_n[0] = g_prof_n[1] = g_prof_n[2] = 0;
     return SU3_OK;
 }
 
 int32_t su3_profile_read(int32_t kind, double* total_ms, int64_t* launches)
 {
-    if (kind != 0 && kind != 1) return fail(SU3_ERR_ARG, "kind must be 0 or 1");
+    if (kind < 0 || kind > 2) return fail(SU3_ERR_ARG, "kind must be 0, 1 or 2");
     std::lock_guard<std::mutex> lk(g_mu);
     if (total_ms) *total_ms = g_prof_ms[kind];
     if (launches) *launches = g_prof_n[kind];

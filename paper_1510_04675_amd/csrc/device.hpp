@@ -517,7 +517,27 @@ typedef __attribute__((address_space(1))) v4f g_v4f;
 typedef __attribute__((address_space(1))) v2f g_v2f;
 typedef __attribute__((address_space(1))) v2d g_v2d;
 
-template <typename R, int N> __device__ __forceinline__ void load_reals(uintptr_t slab, int cb, R out[N])
+// Vector load / store; NT marks data used once (nontemporal hint, so the
+// caches keep the neighbour links that other threads still need).
+template <bool NT, typename V> __device__ __forceinline__ V vload(uintptr_t a)
+{
+    typedef __attribute__((address_space(1))) V GV;
+    if constexpr (NT)
+        return __builtin_nontemporal_load((const GV*)a);
+    else
+        return *(const GV*)a;
+}
+
+template <bool NT, typename V> __device__ __forceinline__ void vstore(uintptr_t a, V v)
+{
+    typedef __attribute__((address_space(1))) V GV;
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, (GV*)a);
+    else
+        *(GV*)a = v;
+}
+
+template <typename R, int N, bool NT = false> __device__ __forceinline__ void load_reals(uintptr_t slab, int cb, R out[N])
 {
     using L = Rec<R, N>;
     const uintptr_t t = slab + (uintptr_t)(cb >> 5) * L::TB;
@@ -525,28 +545,28 @@ template <typename R, int N> __device__ __forceinline__ void load_reals(uintptr_
     if constexpr (sizeof(R) == 4) {
 #pragma unroll
         for (int c = 0; c < L::NF; c++) {
-            const v4f v = *(const g_v4f*)(q + c * 512);
+            const v4f v = vload<NT, v4f>(q + c * 512);
             out[4 * c] = v.x;
             out[4 * c + 1] = v.y;
             out[4 * c + 2] = v.z;
             out[4 * c + 3] = v.w;
         }
         if constexpr (L::TAIL) {
-            const v2f v = *(const g_v2f*)(t + L::NF * 512 + (uintptr_t)(cb & 31) * 8);
+            const v2f v = vload<NT, v2f>(t + L::NF * 512 + (uintptr_t)(cb & 31) * 8);
             out[4 * L::NF] = v.x;
             out[4 * L::NF + 1] = v.y;
         }
     } else {
 #pragma unroll
         for (int c = 0; c < L::NF; c++) {
-            const v2d v = *(const g_v2d*)(q + c * 512);
+            const v2d v = vload<NT, v2d>(q + c * 512);
             out[2 * c] = v.x;
             out[2 * c + 1] = v.y;
         }
     }
 }
 
-template <typename R, int N> __device__ __forceinline__ void store_reals(uintptr_t slab, int cb, const R in[N])
+template <typename R, int N, bool NT = false> __device__ __forceinline__ void store_reals(uintptr_t slab, int cb, const R in[N])
 {
     using L = Rec<R, N>;
     const uintptr_t t = slab + (uintptr_t)(cb >> 5) * L::TB;
@@ -554,12 +574,12 @@ template <typename R, int N> __device__ __forceinline__ void store_reals(uintptr
     if constexpr (sizeof(R) == 4) {
 #pragma unroll
         for (int c = 0; c < L::NF; c++)
-            *(g_v4f*)(q + c * 512) = v4f{ in[4 * c], in[4 * c + 1], in[4 * c + 2], in[4 * c + 3] };
+            vstore<NT, v4f>(q + c * 512, v4f{ in[4 * c], in[4 * c + 1], in[4 * c + 2], in[4 * c + 3] });
         if constexpr (L::TAIL)
-            *(g_v2f*)(t + L::NF * 512 + (uintptr_t)(cb & 31) * 8) = v2f{ in[4 * L::NF], in[4 * L::NF + 1] };
+            vstore<NT, v2f>(t + L::NF * 512 + (uintptr_t)(cb & 31) * 8, v2f{ in[4 * L::NF], in[4 * L::NF + 1] });
     } else {
 #pragma unroll
-        for (int c = 0; c < L::NF; c++) *(g_v2d*)(q + c * 512) = v2d{ in[2 * c], in[2 * c + 1] };
+        for (int c = 0; c < L::NF; c++) vstore<NT, v2d>(q + c * 512, v2d{ in[2 * c], in[2 * c + 1] });
     }
 }
 
@@ -570,10 +590,10 @@ template <typename R, int NC> struct Links {
     __device__ __forceinline__ uintptr_t slab_at(int s) const { return p + (uintptr_t)s * sb; }
 };
 
-template <typename R, int NC> __device__ __forceinline__ M3<R> load_link(uintptr_t slab, int cb)
+template <typename R, int NC, bool NT = false> __device__ __forceinline__ M3<R> load_link(uintptr_t slab, int cb)
 {
     R b[NC];
-    load_reals<R, NC>(slab, cb, b);
+    load_reals<R, NC, NT>(slab, cb, b);
     M3<R> m;
 #pragma unroll
     for (int k = 0; k < NC / 2; k++) {
@@ -584,7 +604,7 @@ template <typename R, int NC> __device__ __forceinline__ M3<R> load_link(uintptr
     return m;
 }
 
-template <typename R, int NC> __device__ __forceinline__ void store_link(uintptr_t slab, int cb, const M3<R>& m)
+template <typename R, int NC, bool NT = false> __device__ __forceinline__ void store_link(uintptr_t slab, int cb, const M3<R>& m)
 {
     R b[NC];
 #pragma unroll
@@ -592,7 +612,7 @@ template <typename R, int NC> __device__ __forceinline__ void store_link(uintptr
         b[2 * k] = m.re[k];
         b[2 * k + 1] = m.im[k];
     }
-    store_reals<R, NC>(slab, cb, b);
+    store_reals<R, NC, NT>(slab, cb, b);
 }
 
 // Convenience: load U_mu at site coordinates n (any parity).
@@ -613,8 +633,11 @@ __device__ __forceinline__ M3<C> staple_sum(const Links<R, NC>& U, const Geo& g,
 {
     M3<C> A;
     m_set_zero(A);
-    int npm[4] = { n[0], n[1], n[2], n[3] };
-    npm[mu] = wrap_add(n[mu], 1, g.L[mu]);
+    // n + mu with mu known only at run time: selects over the unrolled
+    // components keep the coordinates in registers (no indexed array)
+    int npm[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) npm[k] = (k == mu) ? wrap_add(n[k], 1, g.L[k]) : n[k];
 #pragma unroll
     for (int nu = 0; nu < 4; nu++) {
         if (nu == mu) continue;

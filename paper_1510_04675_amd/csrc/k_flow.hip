@@ -87,7 +87,11 @@ __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double 
     X.im[7] = x[7];
     const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N>(X);
     const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
-    store_link<R, NC>(D.slab(mu, par), cb, m_mul(E, w));
+    M3<R> wn = m_mul(E, w);
+    // A 12-real record rebuilds row 2 from rows 0 and 1, so their rounding
+    // would feed back through every later product: re-orthonormalize first.
+    if constexpr (NC == 12) m_reunit(wn);
+    store_link<R, NC>(D.slab(mu, par), cb, wn);
 }
 
 hipError_t launch_flow_stage(int prec, const Grid& gr, double eps, double cz, double ca, int first, hipStream_t st)

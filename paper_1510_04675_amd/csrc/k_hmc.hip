@@ -135,7 +135,11 @@ __global__ void __launch_bounds__(256) k_kick_drift(Grid gr, double eps_kick, do
     if (drift) {
         const M3<R> E = m_exp_ah<R, ExpOrder<R>::N>(i_eps_P(p, (R)eps_drift));
         const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
-        store_link<R, NC>(D.slab(x.mu, x.par), x.cb, m_mul(E, u));
+        M3<R> un = m_mul(E, u);
+        // 12-real records: row 2 is rebuilt from rows 0 and 1, so keep them
+        // orthonormal (their rounding would otherwise feed back).
+        if constexpr (NC == 12) m_reunit(un);
+        store_link<R, NC>(D.slab(x.mu, x.par), x.cb, un);
     }
 }
 

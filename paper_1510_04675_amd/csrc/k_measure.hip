@@ -3,7 +3,7 @@
 // of 256 threads, one site per thread, a wavefront shuffle tree, then one
 // final block per lattice that adds the block partials in a fixed order, so
 // results are bitwise reproducible and independent of the launch shapes
-// chosen for the update kernels.
+// chosen for the update kernels and of the hardware block order.
 #include "kernels.hpp"
 
 namespace msmc {
@@ -35,21 +35,40 @@ __device__ __forceinline__ double block_sum_256(double v)
 }
 
 struct SiteIdx {
-    int l, n[4];
+    int l, lb, n[4];
     bool valid;
 };
 
+// Site of this thread.  Both parities are interleaved: sites are walked in
+// tiles of L0 x ty x tz x tt (tiles ordered y, z, t; inside a tile x fastest,
+// then y, z, t), so the forward neighbours a site reads are the own links of
+// threads that run at nearly the same time on the same XCD.  The mapping
+// depends only on the logical block, and block partials are stored by
+// logical block, so sums do not depend on the hardware block order.
 __device__ __forceinline__ SiteIdx site_index(const Grid& gr)
 {
     SiteIdx s;
-    const int lb = blockIdx.x;  // reductions are not remapped
-    s.l = find_lattice_m(gr.bbeg, gr.nlat, lb);
-    const Geo g = gr.descs[s.l].g;
-    const int e = (lb - gr.bbeg[s.l]) * 256 + (int)threadIdx.x;
+    s.lb = logical_block(blockIdx.x, gr.nblocks, gr.remap);
+    s.l = find_lattice_m(gr.bbeg, gr.nlat, s.lb);
+    const LatDesc& d = gr.descs[s.l];
+    const Geo g = d.g;
+    const int e = (s.lb - gr.bbeg[s.l]) * 256 + (int)threadIdx.x;
     s.valid = e < 2 * g.Vh;
     if (s.valid) {
-        const int par = e >= g.Vh ? 1 : 0;
-        cb_coords(g, e - par * g.Vh, par, s.n);
+        const int ty = d.mtile[0], tz = d.mtile[1], tt = d.mtile[2];
+        const int th = g.L[0] * ty * tz * tt;
+        const int tid = e / th, j = e - tid * th;
+        const int ny = g.L[1] / ty, nz = g.L[2] / tz;
+        const int iy = tid % ny, r = tid / ny;
+        const int iz = r % nz, it = r / nz;
+        s.n[0] = j % g.L[0];
+        int q = j / g.L[0];
+        const int ly = q % ty;
+        q /= ty;
+        const int lz = q % tz, lt = q / tz;
+        s.n[1] = iy * ty + ly;
+        s.n[2] = iz * tz + lz;
+        s.n[3] = it * tt + lt;
     }
     return s;
 }
@@ -70,7 +89,63 @@ __device__ __forceinline__ void shifted(const int n[4], const Geo& g, int mu, in
     if (snu) out[nu] = wrap_add(out[nu], snu, g.L[nu]);
 }
 
+// Rows 0 and 1 of X = A B for a 12-real A (rows 0, 1 only) and a full B,
+// in fp32 with explicit fused multiply-adds.
+__device__ __forceinline__ void rows01_mul(const float a[12], const M3<float>& b, float xr[6], float xi[6])
+{
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float ar = a[6 * r + 2 * k], ai = a[6 * r + 2 * k + 1];
+                re = fmaf(ar, b.re[3 * k + c], re);
+                re = fmaf(-ai, b.im[3 * k + c], re);
+                im = fmaf(ar, b.im[3 * k + c], im);
+                im = fmaf(ai, b.re[3 * k + c], im);
+            }
+            xr[3 * r + c] = re;
+            xi[3 * r + c] = im;
+        }
+}
+
+// Re Tr(X Y^+) for X, Y in SU(3) from their rows 0 and 1 alone.  With
+// s_ij = sum_k X_ik conj(Y_jk) (i, j = 0, 1) the third rows, being
+// conj(row0 x row1), contribute conj(s00 s11 - s01 s10); hence
+// Re Tr(X Y^+) = Re(s00 + s11 + s00 s11 - s01 s10).
+__device__ __forceinline__ float retr_rows01(const float xr[6], const float xi[6], const float yr[6], const float yi[6])
+{
+    float sr[2][2], si[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                re = fmaf(xr[3 * i + k], yr[3 * j + k], re);
+                re = fmaf(xi[3 * i + k], yi[3 * j + k], re);
+                im = fmaf(xi[3 * i + k], yr[3 * j + k], im);
+                im = fmaf(-xr[3 * i + k], yi[3 * j + k], im);
+            }
+            sr[i][j] = re;
+            si[i][j] = im;
+        }
+    float t = sr[0][0] + sr[1][1];
+    t = fmaf(sr[0][0], sr[1][1], t);
+    t = fmaf(-si[0][0], si[1][1], t);
+    t = fmaf(-sr[0][1], sr[1][0], t);
+    t = fmaf(si[0][1], si[1][0], t);
+    return t;
+}
+
 // sum_{mu<nu} [1 - (1/3) Re Tr U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+]
+// Each plane term is formed per site and summed in fp64.  18-real fields
+// multiply in fp64; 12-real fields, whose third rows are by construction
+// conj(row0 x row1), form only rows 0 and 1 of the two half-plaquettes in
+// fp32 (the SU(3) identity above).
 template <typename R, int NC> __global__ void __launch_bounds__(256) k_plaq(Grid gr, double* __restrict__ partials)
 {
     const SiteIdx s = site_index(gr);
@@ -78,26 +153,48 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_plaq(Grid
     if (s.valid) {
         const LatDesc& d = gr.descs[s.l];
         const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
+        if constexpr (NC == 12) {
+            const int cb = lex_index(d.g, s.n) >> 1;
+            const int par = (s.n[0] + s.n[1] + s.n[2] + s.n[3]) & 1;
+            float own[4][12];
 #pragma unroll
-        for (int mu = 0; mu < 4; mu++) {
-            int npm[4];
-            shifted(s.n, d.g, mu, 1, 0, 0, npm);
-            const M3<double> umu = ld_d(U, d.g, mu, s.n);
+            for (int mu = 0; mu < 4; mu++) load_reals<float, 12>(U.slab(mu, par), cb, own[mu]);
 #pragma unroll
-            for (int nu = mu + 1; nu < 4; nu++) {
-                int npn[4];
-                shifted(s.n, d.g, nu, 1, 0, 0, npn);
-                const M3<double> X = m_mul(umu, ld_d(U, d.g, nu, npm));
-                const M3<double> Y = m_mul(ld_d(U, d.g, nu, s.n), ld_d(U, d.g, mu, npn));
-                double t = 0.0;
+            for (int mu = 0; mu < 4; mu++) {
+                int npm[4];
+                shifted(s.n, d.g, mu, 1, 0, 0, npm);
 #pragma unroll
-                for (int k = 0; k < 9; k++) t += X.re[k] * Y.re[k] + X.im[k] * Y.im[k];
-                acc += 1.0 - t / 3.0;
+                for (int nu = mu + 1; nu < 4; nu++) {
+                    int npn[4];
+                    shifted(s.n, d.g, nu, 1, 0, 0, npn);
+                    float xr[6], xi[6], yr[6], yi[6];
+                    rows01_mul(own[mu], load_at(U, d.g, nu, npm), xr, xi);
+                    rows01_mul(own[nu], load_at(U, d.g, mu, npn), yr, yi);
+                    acc += 1.0 - (double)retr_rows01(xr, xi, yr, yi) / 3.0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int mu = 0; mu < 4; mu++) {
+                int npm[4];
+                shifted(s.n, d.g, mu, 1, 0, 0, npm);
+                const M3<double> umu = ld_d(U, d.g, mu, s.n);
+#pragma unroll
+                for (int nu = mu + 1; nu < 4; nu++) {
+                    int npn[4];
+                    shifted(s.n, d.g, nu, 1, 0, 0, npn);
+                    const M3<double> X = m_mul(umu, ld_d(U, d.g, nu, npm));
+                    const M3<double> Y = m_mul(ld_d(U, d.g, nu, s.n), ld_d(U, d.g, mu, npn));
+                    double t = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 9; k++) t += X.re[k] * Y.re[k] + X.im[k] * Y.im[k];
+                    acc += 1.0 - t / 3.0;
+                }
             }
         }
     }
     acc = block_sum_256(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+    if (threadIdx.x == 0) partials[s.lb] = acc;
 }
 
 // Clover field strength: traceless part of (Q - Q^+)/8, Q the sum of the
@@ -186,7 +283,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_qtop(Grid
         acc = -t / (2.0 * M_PI * M_PI);
     }
     acc = block_sum_256(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+    if (threadIdx.x == 0) partials[s.lb] = acc;
 }
 
 // sum_{mu<nu} -Re Tr(F_munu F_munu) per site
@@ -204,7 +301,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_energy(Gr
             }
     }
     acc = block_sum_256(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+    if (threadIdx.x == 0) partials[s.lb] = acc;
 }
 
 // One block per lattice: out[l * stride + off] = sum of its partials.

@@ -27,6 +27,7 @@ struct LatDesc {
     double beta;
     uint32_t seed, lid;
     int tile[3];   // (ty, tz, tt): site tile of the phase kernels (divisors of L1, L2, L3)
+    int mtile[3];  // (ty, tz, tt): site tile of the measurement kernels, fixed by the extents
 };
 
 // Block partition: lattice l owns logical blocks [bbeg[l], bbeg[l+1]).

@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
     const int cb = lex_index(g, n) >> 1;
     const M3<R> A = staple_sum<R, NC, R>(U, g, mu, n);
     const uintptr_t s = U.slab(mu, par);
-    M3<R> u = load_link<R, NC>(s, cb);
+    M3<R> u = load_link<R, NC, true>(s, cb);
     M3<R> W = m_mul(u, A);
 
     Rng rng{ d.seed, d.lid, (uint32_t)lex_index(g, n), 0 };
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
     // before every store: rounding in a 12-real record would otherwise grow,
     // because the rebuilt third row feeds back into rows 0 and 1.
     if constexpr (!kF64) m_reunit(u);
-    store_link<R, NC>(s, cb, u);
+    store_link<R, NC, true>(s, cb, u);
 }
 
 template <typename R, int NC, int KIND>
