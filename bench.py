@@ -174,7 +174,7 @@ def main():
     ap.add_argument("--lattice", type=int, default=32)
     ap.add_argument("--batch", type=int, default=4, help="lattices in the FP32 batched run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of variants to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch)")
+    ap.add_argument("--only", default="", help="comma list of parts to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch,hmc)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-hmc", action="store_true", help="skip the HMC report")
@@ -212,12 +212,15 @@ def main():
         log(f"bench: {name}: {res[name]['updates_per_s']:.3e} link updates/s, "
             f"OR kernel {res[name]['or_kernel_us']:.1f} us, HB kernel {res[name]['hb_kernel_us']:.1f} us, "
             f"plaquette kernel {res[name]['plaq_kernel_us']:.1f} us")
-    head = res.get("r12_batch") or next(iter(res.values()))
+    head = res.get("r12_batch") or next(iter(res.values()), None)
     hmc = None
-    if not a.no_hmc and not a.only:
+    if not a.no_hmc and (not a.only or "hmc" in want):
         log("bench: hmc (32^4, tau 1, 40 steps, 20 trajectories) ...")
         hmc = run_hmc(m, torch, dims)
         log(f"bench: hmc {hmc['trajectories_per_s']} traj/s, acceptance {hmc['acceptance']}")
+    if head is None:  # only the HMC part was asked for
+        print(json.dumps({"hmc": hmc}), flush=True)
+        return
     cpu = None
     if not a.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)

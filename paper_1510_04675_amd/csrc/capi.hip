@@ -151,14 +151,15 @@ struct Plan {
     int* d_bbeg_phase = nullptr;
     int* d_bbeg_link = nullptr;
     int* d_bbeg_site = nullptr;
-    int nblk_phase = 0, nblk_link = 0, nblk_site = 0;
+    int* d_bbeg_lw = nullptr;
+    int nblk_phase = 0, nblk_link = 0, nblk_site = 0, nblk_lw = 0;
     double* d_partials = nullptr;
     double* d_out = nullptr;  // reduction results
     int out_cap = 0;
     uint64_t* d_sweep = nullptr;
     unsigned long long* d_exh = nullptr;
     std::vector<LatDesc> host_descs;
-    std::vector<int> bbeg_phase_h, bbeg_link_h, bbeg_site_h;
+    std::vector<int> bbeg_phase_h, bbeg_link_h, bbeg_site_h, bbeg_lw_h;
 
     void release()
     {
@@ -166,12 +167,13 @@ struct Plan {
         hipFree(d_bbeg_phase);
         hipFree(d_bbeg_link);
         hipFree(d_bbeg_site);
+        hipFree(d_bbeg_lw);
         hipFree(d_partials);
         hipFree(d_out);
         hipFree(d_sweep);
         hipFree(d_exh);
         d_descs = nullptr;
-        d_bbeg_phase = d_bbeg_link = d_bbeg_site = nullptr;
+        d_bbeg_phase = d_bbeg_link = d_bbeg_site = d_bbeg_lw = nullptr;
         d_partials = d_out = nullptr;
         d_sweep = nullptr;
         d_exh = nullptr;
@@ -185,6 +187,11 @@ struct Plan {
     Grid grid_site(const LatDesc* descs = nullptr) const
     {
         return Grid{ descs ? descs : d_descs, d_bbeg_site, nlat, nblk_site, 256, 1 };
+    }
+    // all 4V links, four directions of 64 sites per block (link_walk)
+    Grid grid_lw(const LatDesc* descs = nullptr) const
+    {
+        return Grid{ descs ? descs : d_descs, d_bbeg_lw, nlat, nblk_lw, 256, 1 };
     }
 };
 
@@ -254,6 +261,9 @@ static LatDesc base_desc(const su3_field_s* f)
     d.cs = f->cs;
     d.cs8 = f->cs8;
     d.g = f->geo();
+    d.tile[0] = largest_divisor_upto(f->L[1], 16);  // plans replace it with the launch choice
+    d.tile[1] = largest_divisor_upto(f->L[2], 8);
+    d.tile[2] = largest_divisor_upto(f->L[3], 4);
     d.mtile[0] = largest_divisor_upto(f->L[1], 8);
     d.mtile[1] = largest_divisor_upto(f->L[2], 8);
     d.mtile[2] = largest_divisor_upto(f->L[3], 4);
@@ -278,6 +288,7 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
     p.bbeg_phase_h.assign(1, 0);
     p.bbeg_link_h.assign(1, 0);
     p.bbeg_site_h.assign(1, 0);
+    p.bbeg_lw_h.assign(1, 0);
     for (auto* f : fs) {
         LatDesc d = base_desc(f);
         d.tile[0] = largest_divisor_upto(f->L[1], cfg.ty);
@@ -287,15 +298,18 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
         p.bbeg_phase_h.push_back(p.bbeg_phase_h.back() + ceil_div(f->Vh, phase_block));
         p.bbeg_link_h.push_back(p.bbeg_link_h.back() + ceil_div(8LL * f->Vh, 256));
         p.bbeg_site_h.push_back(p.bbeg_site_h.back() + ceil_div(2LL * f->Vh, 256));
+        p.bbeg_lw_h.push_back(p.bbeg_lw_h.back() + 2 * ceil_div(f->Vh, 64));
     }
     p.nblk_phase = p.bbeg_phase_h.back();
     p.nblk_link = p.bbeg_link_h.back();
     p.nblk_site = p.bbeg_site_h.back();
+    p.nblk_lw = p.bbeg_lw_h.back();
     if (!p.d_descs) {
         HIPCHK(hipMalloc(&p.d_descs, sizeof(LatDesc) * p.nlat));
         HIPCHK(hipMalloc(&p.d_bbeg_phase, sizeof(int) * (p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_bbeg_link, sizeof(int) * (p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_bbeg_site, sizeof(int) * (p.nlat + 1)));
+        HIPCHK(hipMalloc(&p.d_bbeg_lw, sizeof(int) * (p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_partials, sizeof(double) * std::max(p.nblk_site, p.nblk_link)));
         HIPCHK(hipMalloc(&p.d_sweep, sizeof(uint64_t)));
         HIPCHK(hipMalloc(&p.d_exh, sizeof(unsigned long long)));
@@ -310,6 +324,7 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
     HIPCHK(upload_ints(p.d_bbeg_phase, p.bbeg_phase_h, st));
     HIPCHK(upload_ints(p.d_bbeg_link, p.bbeg_link_h, st));
     HIPCHK(upload_ints(p.d_bbeg_site, p.bbeg_site_h, st));
+    HIPCHK(upload_ints(p.d_bbeg_lw, p.bbeg_lw_h, st));
     return SU3_OK;
 }
 
@@ -1147,10 +1162,10 @@ int32_t su3_hmc_trajectory(su3_field f, double beta, double tau, int32_t n_steps
     int cur = 0;  // descriptor whose U holds the current links
     for (int k = 0; k < n_steps; k++) {
         const double ek = (k == 0) ? 0.5 * eps : eps;
-        HIPCHK(launch_kick_drift(f->prec, p.grid_link(f->d_extra + cur), ek, eps, 1, st));
+        HIPCHK(launch_kick_drift(f->prec, p.grid_lw(f->d_extra + cur), ek, eps, 1, st));
         cur = (cur == 1) ? 2 : 1;
     }
-    HIPCHK(launch_kick_drift(f->prec, p.grid_link(f->d_extra + cur), 0.5 * eps, 0.0, 0, st));
+    HIPCHK(launch_kick_drift(f->prec, p.grid_lw(f->d_extra + cur), 0.5 * eps, 0.0, 0, st));
     HIPCHK(launch_kinetic_partial(f->prec, g0, p.d_partials, st));
     HIPCHK(launch_reduce_final(g0, p.d_partials, p.d_out, 1, 2, st));
     HIPCHK(launch_plaq_partial(f->prec, p.grid_site(f->d_extra + cur), p.d_partials, st));
@@ -1201,7 +1216,7 @@ int32_t su3_wilson_flow(su3_field f, double eps, int32_t n_steps)
     int cur = 0;
     for (int s = 0; s < n_steps; s++)
         for (int k = 0; k < 3; k++) {
-            HIPCHK(launch_flow_stage(f->prec, f->plan.grid_link(f->d_extra + 3 + cur), eps, cz[k], ca[k], k == 0, st));
+            HIPCHK(launch_flow_stage(f->prec, f->plan.grid_lw(f->d_extra + 3 + cur), eps, cz[k], ca[k], k == 0, st));
             cur ^= 1;
         }
     if (cur == 1) HIPCHK(hipMemcpyAsync(f->data, f->alt[0], f->bytes, hipMemcpyDeviceToDevice, st));

@@ -12,37 +12,21 @@
 
 namespace msmc {
 
-__device__ __forceinline__ int find_lattice_f(const int* __restrict__ bbeg, int nlat, int lb)
-{
-    int lo = 0, hi = nlat - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (bbeg[mid] <= lb)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
 template <typename R> struct FlowExpOrder;
 template <> struct FlowExpOrder<double> { static constexpr int N = 12; };
-template <> struct FlowExpOrder<float> { static constexpr int N = 8; };
+// fp32: X is scaled to norm <= 1/4, where the order-6 remainder (< 1/4^7/7!,
+// about 1.2e-8) is below fp32 rounding.
+template <> struct FlowExpOrder<float> { static constexpr int N = 6; };
 
 template <typename R, int NC>
 __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double cz, double ca, int first)
 {
-    const int lb = logical_block(blockIdx.x, gr.nblocks, gr.remap);
-    const int l = find_lattice_f(gr.bbeg, gr.nlat, lb);
-    const LatDesc& d = gr.descs[l];
-    const int Vh = d.g.Vh;
-    const int e = (lb - gr.bbeg[l]) * (int)blockDim.x + (int)threadIdx.x;
-    if (e >= 8 * Vh) return;
-    const int slab = e / Vh, cb = e - slab * Vh, mu = slab >> 1, par = slab & 1;
+    const LinkWalk lw = link_walk(gr);
+    if (!lw.valid) return;
+    const LatDesc& d = gr.descs[lw.l];
+    const int mu = lw.mu, par = lw.par, cb = lw.cb, slab = 2 * mu + par;
     const Links<R, NC> W{ (uintptr_t)d.U, d.cs };
-    int n[4];
-    cb_coords(d.g, cb, par, n);
-    const M3<R> A = staple_sum<R, NC, R>(W, d.g, mu, n);
+    const M3<R> A = staple_sum<R, NC, R>(W, d.g, mu, lw.n);
     const M3<R> w = load_link<R, NC>(W.slab(mu, par), cb);
     const M3<R> Om = m_mul(w, A);
     // Z in 8-real form

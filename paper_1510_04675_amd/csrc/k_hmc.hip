@@ -100,18 +100,18 @@ template <typename R> __device__ __forceinline__ M3<R> i_eps_P(const R p[8], R e
 
 template <typename R> struct ExpOrder;
 template <> struct ExpOrder<double> { static constexpr int N = 12; };
-template <> struct ExpOrder<float> { static constexpr int N = 8; };
+// fp32: the argument is scaled to norm <= 1/4, where the order-6 remainder
+// (< 1/4^7/7!, about 1.2e-8) is below fp32 rounding.
+template <> struct ExpOrder<float> { static constexpr int N = 6; };
 
 template <typename R, int NC>
 __global__ void __launch_bounds__(256) k_kick_drift(Grid gr, double eps_kick, double eps_drift, int drift)
 {
-    const LinkIdxH x = link_index_h(gr);
+    const LinkWalk x = link_walk(gr);
     if (!x.valid) return;
     const LatDesc& d = gr.descs[x.l];
     const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
-    int n[4];
-    cb_coords(d.g, x.cb, x.par, n);
-    const M3<R> A = staple_sum<R, NC, R>(U, d.g, x.mu, n);
+    const M3<R> A = staple_sum<R, NC, R>(U, d.g, x.mu, x.n);
     const M3<R> u = load_link<R, NC>(U.slab(x.mu, x.par), x.cb);
     const M3<R> Om = m_mul(u, A);
     const R b6 = (R)(d.beta / 6.0);

@@ -41,6 +41,45 @@ struct Grid {
     int remap;
 };
 
+// Thread -> link for the kernels that update all 4V links at once and read
+// neighbour links (HMC kick-drift, flow stage).  Blocks of 256 threads: the
+// four wavefronts of a block take directions mu = 0..3 of the same 64 sites of
+// one parity, consecutive blocks alternate parity, and the sites follow the
+// tiled checkerboard order of the phase kernels, so the links a staple reads
+// were loaded by nearby threads.  bbeg counts 2 ceil(Vh / 64) blocks per
+// lattice.
+struct LinkWalk {
+    int l, mu, par, cb, n[4];
+    bool valid;
+};
+
+__device__ __forceinline__ LinkWalk link_walk(const Grid& gr)
+{
+    LinkWalk x;
+    const int lb = logical_block(blockIdx.x, gr.nblocks, gr.remap);
+    int lo = 0, hi = gr.nlat - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (gr.bbeg[mid] <= lb)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    x.l = lo;
+    const LatDesc& d = gr.descs[x.l];
+    const int b = lb - gr.bbeg[x.l];
+    x.par = b & 1;
+    x.mu = (int)threadIdx.x >> 6;
+    const int w = (b >> 1) * 64 + ((int)threadIdx.x & 63);
+    x.valid = w < d.g.Vh;
+    x.cb = 0;
+    if (x.valid) {
+        tiled_coords(d.g, d.tile, w, x.par, x.n);
+        x.cb = lex_index(d.g, x.n) >> 1;
+    }
+    return x;
+}
+
 struct HbArgs {
     int n_hits;
     int max_tries;

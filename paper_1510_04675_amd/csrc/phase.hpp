@@ -82,30 +82,6 @@ __device__ __forceinline__ void draw_dir(const Rng& rng, int mu, int sg, int h, 
     g[3] = sr * ct;
 }
 
-// Thread index w -> site of the given parity, walking the lattice in tiles of
-// L0 x ty x tz x tt sites (tiles ordered y, z, t; inside a tile x-halves
-// fastest, then y, z, t).  Whole x rows keep each wavefront's loads
-// contiguous; the tile shape sets which neighbours are in flight together on
-// one XCD.  ty = L1, tz = L2, tt = 1 is the plain lexicographic order.
-__device__ __forceinline__ void tiled_coords(const Geo& g, const int tile[3], int w, int par, int n[4])
-{
-    const int ty = tile[0], tz = tile[1], tt = tile[2];
-    const int th = g.h0 * ty * tz * tt;
-    const int tid = w / th, j = w - tid * th;
-    const int ny = g.L[1] / ty, nz = g.L[2] / tz;
-    const int iy = tid % ny, r = tid / ny;
-    const int iz = r % nz, it = r / nz;
-    const int x0h = j % g.h0;
-    int q = j / g.h0;
-    const int ly = q % ty;
-    q /= ty;
-    const int lz = q % tz, lt = q / tz;
-    n[1] = iy * ty + ly;
-    n[2] = iz * tz + lz;
-    n[3] = it * tt + lt;
-    n[0] = 2 * x0h + ((par + n[1] + n[2] + n[3]) & 1);
-}
-
 template <typename R, int NC, int KIND>
 __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const uint64_t* __restrict__ sweep_base,
                                                int sweep_off, HbArgs hb, unsigned long long* exhausted)
