@@ -28,6 +28,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 LINK_BYTES = {"fp64": 144, "fp32": 72, "fp32_r12": 48}
 PHASE_RECORDS = 9  # 8 link records read + 1 written per updated link (4V reads + V/2 writes per phase)
+# Sources that determine the phase kernel's code; the committed counter
+# summary records their hash, and its HBM traffic is reported only while
+# they are unchanged.
+KERNEL_SOURCES = ["paper_1510_04675_amd/csrc/phase.hpp", "paper_1510_04675_amd/csrc/device.hpp",
+                  "paper_1510_04675_amd/csrc/kernels.hpp", "paper_1510_04675_amd/csrc/k_phase_f32.hip",
+                  "paper_1510_04675_amd/csrc/k_phase_f64.hip", "paper_1510_04675_amd/build.py"]
+TRAFFIC_SUMMARY = "profiles/k_phase_hb_or_32x4.md"
 
 
 def log(msg):
@@ -84,8 +91,11 @@ def run_variant(m, torch, prec, n_lat, dims, steps, warmup, beta=6.0, n_or=4):
         "plaq_kernel_us": 1e3 * pl_ms / max(pl_n, 1),
         "hb_launches": hb_n, "or_launches": or_n, "plaq_last": float(plaq[-1].mean()),
         "phase_links": V // 2 * n_lat, "plaq_first": plaq_first,
+        # algorithmic bytes of all overrelaxation launches of the profiled steps
+        "or_bytes_total": steps * n_or * 8 * (V // 2 * n_lat) * PHASE_RECORDS * LINK_BYTES[prec],
         "sweeps_per_s": n_lat * steps / wall,
-        "hb_updates_per_s": (V // 2 * n_lat) / (1e-3 * hb_ms / max(hb_n, 1)),
+        # heat-bath link updates per second of heat-bath kernel time
+        "hb_updates_per_s": steps * 8 * (V // 2 * n_lat) / max(1e-3 * hb_ms, 1e-12),
     }
     for f in fields:
         f.close()
@@ -129,12 +139,43 @@ def run_hmc(m, torch, dims, n_traj=20, n_steps=40, beta=6.0, therm=200, prec="fp
     return out
 
 
-def roofline(v):
-    per_launch = v["phase_links"] * PHASE_RECORDS * LINK_BYTES[v["prec"]]
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def launch_str(c):
+    return f"{c['block']},{c['xcd_remap']},{c['ty']},{c['tz']},{c['tt']}"
+
+
+def recorded_traffic(v, lattice):
+    """HBM bytes per launch of the OR phase kernel (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, each scaled by a plain copy's reading), from the committed
+    summary, if it was taken with these kernel sources, this workload and this
+    launch shape; otherwise None."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_SUMMARY)) as fh:
+            rec = next(json.loads(line.split(":", 1)[1]) for line in fh if line.startswith("traffic-record:"))
+    except (OSError, StopIteration, ValueError):
+        return None
+    same = (rec.get("sources_sha256") == kernel_sources_hash() and rec.get("launch") == launch_str(v["launch"])
+            and rec.get("prec") == v["prec"] and rec.get("n_lat") == v["n_lat"] and rec.get("lattice") == lattice)
+    return rec.get("hbm_bytes_per_launch") if same else None
+
+
+def roofline(v, lattice=32):
+    # a batch may be swept in lattice groups, one launch per group and phase:
+    # bytes per launch = all overrelaxation bytes / overrelaxation launches
+    per_launch = v["or_bytes_total"] / max(v["or_launches"], 1)
     achieved = per_launch / (v["or_kernel_us"] * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_phase<{v['prec']}, OR>", "algorithmic_bytes_per_launch": per_launch,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(v, lattice),
+            "traffic_unit": "bytes per launch", "traffic_source": TRAFFIC_SUMMARY,
+            "kernel": f"k_phase<{v['prec']}, OR>", "algorithmic_bytes_per_launch": round(per_launch),
             "avg_launch_us": round(v["or_kernel_us"], 2)}
 
 
@@ -243,7 +284,7 @@ def main():
         "config": {"workload": f"HB+OR sweeps (1 HB + 4 OR), {head['n_lat']} x {L}^4, {head['prec']} links",
                    "lattice": f"{L}^4", "n_lattices": head["n_lat"], "storage": head["prec"], "beta": 6.0,
                    "n_or": 4, "sampler": "Kennedy-Pendleton", "parallelism": "single GPU"},
-        "roofline": roofline(head),
+        "roofline": roofline(head, L),
         "cpu_baseline": cpu,
         "variants": {k: {"link_updates_per_s": round(v["updates_per_s"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                          "or_kernel_us": round(v["or_kernel_us"], 2), "hb_kernel_us": round(v["hb_kernel_us"], 2),
@@ -251,7 +292,7 @@ def main():
                          "sweeps_per_s": round(v["sweeps_per_s"], 2),
                          "hb_kernel_link_updates_per_s": round(v["hb_updates_per_s"], 1),
                          "first_sweep_plaquette_lattice0": v["plaq_first"],
-                         "or_hbm_frac": roofline(v)["frac"], "plaq_after": round(v["plaq_last"], 8),
+                         "or_hbm_frac": roofline(v, L)["frac"], "plaq_after": round(v["plaq_last"], 8),
                          "launch": v["launch"]}
                      for k, v in res.items()},
     }

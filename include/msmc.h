@@ -193,11 +193,21 @@ int32_t su3_last_exhausted(su3_field f, int64_t* count);
 /* Launch shape of the checkerboard phase kernels: block in {64, 128, 256,
  * 512}, xcd_remap in {0, 1}; block = 0 restores automatic choice.
  * Results do not depend on it.  su3_autotune(1) makes the next sweep call
- * time the candidates on scratch fields of the same shapes and keep the
- * fastest for those shapes. */
+ * time the candidates (3 blocks x 2 remaps x 7 tiles) on cold-start scratch
+ * fields of the same shapes with 1 HB + 4 OR sweeps and keep the fastest for
+ * those shapes; the default (256, remap, tile 16 x 8 x 4) is kept unless
+ * another shape is faster by more than 1.5 %.  The scratch fields are
+ * allocated and freed inside that call. */
 int32_t su3_set_launch(int32_t block, int32_t xcd_remap);
 int32_t su3_autotune(int32_t enable);
 int32_t su3_get_launch(int32_t* block, int32_t* xcd_remap);
+
+/* Batched sweeps run lattice groups one after another, each group's
+ * links at most `bytes` (a larger lattice forms a group alone), all passes
+ * of a sweep per group, so that a group stays in the last-level cache
+ * (256 MB on MI355X) between phases.  0 sweeps the whole batch phase by
+ * phase.  Default 224 MiB.  Results do not depend on it. */
+int32_t su3_set_group_bytes(uint64_t bytes);
 
 /* Site tile of the checkerboard phase kernels: threads walk each lattice in
  * tiles of L0 x ty x tz x tt sites (each extent clamped to the largest

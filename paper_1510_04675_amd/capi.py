@@ -65,6 +65,7 @@ SIGNATURES = {
     "su3_get_config": (_i32, [_p, _i32, _p]),
     "su3_profile_enable": (_i32, [_i32]),
     "su3_profile_read": (_i32, [_i32, C.POINTER(_d), C.POINTER(_i64)]),
+    "su3_set_group_bytes": (_i32, [C.c_uint64]),
     "su3_last_error": (C.c_char_p, []),
 }
 
@@ -295,6 +296,10 @@ def su3_get_launch():
     b, r = C.c_int32(), C.c_int32()
     _ck(lib().su3_get_launch(C.byref(b), C.byref(r)))
     return b.value, r.value
+
+
+def su3_set_group_bytes(nbytes: int):
+    _ck(lib().su3_set_group_bytes(int(nbytes)))
 
 
 def su3_set_tile(ty: int, tz: int, tt: int):

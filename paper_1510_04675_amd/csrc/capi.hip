@@ -153,6 +153,11 @@ struct Plan {
     int* d_bbeg_site = nullptr;
     int* d_bbeg_lw = nullptr;
     int nblk_phase = 0, nblk_link = 0, nblk_site = 0, nblk_lw = 0;
+    // Lattice groups of the sweep schedule: group g holds lattices
+    // [grp_first[g], grp_first[g + 1]) and its phase blocks are counted by
+    // d_bbeg_grp + grp_off[g] (starting at 0).
+    std::vector<int> grp_first, grp_off, grp_nblk;
+    int* d_bbeg_grp = nullptr;
     double* d_partials = nullptr;
     double* d_out = nullptr;  // reduction results
     int out_cap = 0;
@@ -168,18 +173,28 @@ struct Plan {
         hipFree(d_bbeg_link);
         hipFree(d_bbeg_site);
         hipFree(d_bbeg_lw);
+        hipFree(d_bbeg_grp);
         hipFree(d_partials);
         hipFree(d_out);
         hipFree(d_sweep);
         hipFree(d_exh);
         d_descs = nullptr;
-        d_bbeg_phase = d_bbeg_link = d_bbeg_site = d_bbeg_lw = nullptr;
+        d_bbeg_phase = d_bbeg_link = d_bbeg_site = d_bbeg_lw = d_bbeg_grp = nullptr;
+        grp_first.clear();
+        grp_off.clear();
+        grp_nblk.clear();
         d_partials = d_out = nullptr;
         d_sweep = nullptr;
         d_exh = nullptr;
         out_cap = 0;
     }
     Grid grid_phase() const { return Grid{ d_descs, d_bbeg_phase, nlat, nblk_phase, phase_block, remap }; }
+    int ngroups() const { return (int)grp_nblk.size(); }
+    Grid grid_phase_group(int g) const
+    {
+        return Grid{ d_descs + grp_first[g], d_bbeg_grp + grp_off[g], grp_first[g + 1] - grp_first[g], grp_nblk[g],
+                     phase_block, remap };
+    }
     Grid grid_link(const LatDesc* descs = nullptr) const
     {
         return Grid{ descs ? descs : d_descs, d_bbeg_link, nlat, nblk_link, 256, 1 };
@@ -273,6 +288,12 @@ static LatDesc base_desc(const su3_field_s* f)
 static int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 // Build or rebuild the device tables of a plan for the given fields.
+// Batches are swept group by group, each group's links at most this many
+// bytes (a lattice larger than that is a group of its own), so that a group
+// stays resident in the 256 MB last-level cache across the phases of a sweep.
+// 0: the whole batch is one group.
+static size_t g_group_bytes = (size_t)224 << 20;
+
 static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const LaunchCfg& cfg, int out_cap,
                           hipStream_t st)
 {
@@ -304,12 +325,35 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
     p.nblk_link = p.bbeg_link_h.back();
     p.nblk_site = p.bbeg_site_h.back();
     p.nblk_lw = p.bbeg_lw_h.back();
+    // lattice groups (consecutive lattices, at most g_group_bytes of links each)
+    std::vector<int> gb;
+    p.grp_first.assign(1, 0);
+    p.grp_off.clear();
+    p.grp_nblk.clear();
+    {
+        size_t acc = 0;
+        for (int i = 0; i < p.nlat; i++) {
+            if (i > p.grp_first.back() && g_group_bytes > 0 && acc + fs[i]->bytes > g_group_bytes) {
+                p.grp_first.push_back(i);
+                acc = 0;
+            }
+            acc += fs[i]->bytes;
+        }
+        p.grp_first.push_back(p.nlat);
+        for (int g = 0; g + 1 < (int)p.grp_first.size(); g++) {
+            const int a = p.grp_first[g], e = p.grp_first[g + 1];
+            p.grp_off.push_back((int)gb.size());
+            for (int i = a; i <= e; i++) gb.push_back(p.bbeg_phase_h[i] - p.bbeg_phase_h[a]);
+            p.grp_nblk.push_back(p.bbeg_phase_h[e] - p.bbeg_phase_h[a]);
+        }
+    }
     if (!p.d_descs) {
         HIPCHK(hipMalloc(&p.d_descs, sizeof(LatDesc) * p.nlat));
         HIPCHK(hipMalloc(&p.d_bbeg_phase, sizeof(int) * (p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_bbeg_link, sizeof(int) * (p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_bbeg_site, sizeof(int) * (p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_bbeg_lw, sizeof(int) * (p.nlat + 1)));
+        HIPCHK(hipMalloc(&p.d_bbeg_grp, sizeof(int) * (2 * p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_partials, sizeof(double) * std::max(p.nblk_site, p.nblk_link)));
         HIPCHK(hipMalloc(&p.d_sweep, sizeof(uint64_t)));
         HIPCHK(hipMalloc(&p.d_exh, sizeof(unsigned long long)));
@@ -325,6 +369,7 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
     HIPCHK(upload_ints(p.d_bbeg_link, p.bbeg_link_h, st));
     HIPCHK(upload_ints(p.d_bbeg_site, p.bbeg_site_h, st));
     HIPCHK(upload_ints(p.d_bbeg_lw, p.bbeg_lw_h, st));
+    HIPCHK(upload_ints(p.d_bbeg_grp, gb, st));
     return SU3_OK;
 }
 
@@ -338,6 +383,7 @@ static bool g_tile_forced = false;
 static bool g_autotune = false;
 static std::map<std::string, LaunchCfg> g_tuned;
 static bool g_profile = false;
+
 static double g_prof_ms[3] = { 0, 0, 0 };
 static long long g_prof_n[3] = { 0, 0, 0 };
 static std::vector<hipEvent_t> g_events;
@@ -399,45 +445,58 @@ struct SweepOpts {
     bool record;
 };
 
+// Records HIP events around one launch when profiling.
+struct ProfMark {
+    std::vector<std::pair<int, int>>* marks;
+    hipStream_t st;
+    int ev = -1;
+    int32_t begin()
+    {
+        if (!marks) return SU3_OK;
+        ev = (int)marks->size() * 2;
+        int32_t rc = ensure_events((size_t)ev + 2);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(g_events[ev], st));
+        return SU3_OK;
+    }
+    int32_t end(int kind)
+    {
+        if (!marks) return SU3_OK;
+        HIPCHK(hipEventRecord(g_events[ev + 1], st));
+        marks->push_back({ ev, kind });
+        return SU3_OK;
+    }
+};
+
 static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, hipStream_t st,
                               std::vector<std::pair<int, int>>* prof_marks)
 {
-    const Grid gph = p.grid_phase();
     const HbArgs hb{ o.n_hits, o.max_tries, o.sampler };
+    const int ng = p.ngroups();
+    int32_t rc;
     for (int k = 0; k < n_sweeps; k++) {
-        for (int pass = 0; pass <= o.n_or; pass++) {
-            const int kind = pass == 0 ? 0 : 1;
-            for (int mu = 0; mu < 4; mu++)
-                for (int par = 0; par < 2; par++) {
-                    int ev = -1;
-                    if (prof_marks) {
-                        ev = (int)prof_marks->size() * 2;
-                        int32_t rc = ensure_events((size_t)ev + 2);
-                        if (rc) return rc;
-                        HIPCHK(hipEventRecord(g_events[ev], st));
+        // Lattices are independent: each group runs its whole sweep before the
+        // next group starts, so its links stay cached between phases.
+        for (int grp = 0; grp < ng; grp++) {
+            const Grid gph = ng > 1 ? p.grid_phase_group(grp) : p.grid_phase();
+            for (int pass = 0; pass <= o.n_or; pass++) {
+                const int kind = pass == 0 ? 0 : 1;
+                for (int mu = 0; mu < 4; mu++)
+                    for (int par = 0; par < 2; par++) {
+                        ProfMark pm{ prof_marks, st };
+                        if ((rc = pm.begin())) return rc;
+                        HIPCHK(launch_phase(p.prec, kind, gph, mu, par, p.d_sweep, k, hb,
+                                            kind == 0 ? p.d_exh : nullptr, st));
+                        if ((rc = pm.end(kind))) return rc;
                     }
-                    HIPCHK(launch_phase(p.prec, kind, gph, mu, par, p.d_sweep, k, hb, kind == 0 ? p.d_exh : nullptr,
-                                        st));
-                    if (prof_marks) {
-                        HIPCHK(hipEventRecord(g_events[ev + 1], st));
-                        prof_marks->push_back({ ev, kind });
-                    }
-                }
+            }
         }
         if (o.reunit_every > 0) HIPCHK(launch_reunit(p.prec, p.grid_link(), p.d_sweep, k, o.reunit_every, st));
         if (o.record) {
-            int ev = -1;
-            if (prof_marks) {
-                ev = (int)prof_marks->size() * 2;
-                int32_t rc = ensure_events((size_t)ev + 2);
-                if (rc) return rc;
-                HIPCHK(hipEventRecord(g_events[ev], st));
-            }
+            ProfMark pm{ prof_marks, st };
+            if ((rc = pm.begin())) return rc;
             HIPCHK(launch_plaq_partial(p.prec, p.grid_site(), p.d_partials, st));
-            if (prof_marks) {
-                HIPCHK(hipEventRecord(g_events[ev + 1], st));
-                prof_marks->push_back({ ev, 2 });
-            }
+            if ((rc = pm.end(2))) return rc;
             HIPCHK(launch_reduce_final(p.grid_site(), p.d_partials, p.d_out, 1, k * p.nlat, st));
         }
     }
@@ -461,8 +520,10 @@ static int32_t validate_hb(const su3_hb_params* pp, SweepOpts& o)
     return SU3_OK;
 }
 
-// Time each launch shape on scratch copies (hot starts) of the given shapes
-// and remember the fastest for this shape set.
+// Time each launch shape on scratch fields (cold starts) of the given shapes
+// with sweeps of 1 HB + 4 OR passes, and remember the fastest for this shape
+// set; the default shape is kept unless another is faster by more than 1.5 %
+// (differences below that are run-to-run noise).
 static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
 {
     std::vector<su3_field_s> scratch(fs.size());
@@ -481,7 +542,7 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
         sp.push_back(&scratch[i]);
     }
     Plan p;
-    std::vector<LaunchCfg> cand;
+    std::vector<LaunchCfg> cand{ default_cfg() };
     const int blocks[] = { 128, 256, 512 };
     const int tiles[][3] = { { 0, 0, 1 }, { 16, 8, 4 }, { 16, 16, 4 }, { 8, 8, 8 }, { 16, 8, 8 }, { 32, 8, 4 }, { 8, 8, 16 } };
     for (int remap = 0; remap < 2; remap++)
@@ -493,9 +554,11 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
                 c.ty = t[0];
                 c.tz = t[1];
                 c.tt = t[2];
+                const LaunchCfg d = default_cfg();
+                if (c.block == d.block && c.remap == d.remap && c.ty == d.ty && c.tz == d.tz && c.tt == d.tt) continue;
                 cand.push_back(c);
             }
-    float best = 1e30f;
+    float best = 1e30f, t_default = 1e30f;
     LaunchCfg bestc = default_cfg();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
@@ -507,13 +570,13 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
             if (ci == 0) {
                 for (size_t i = 0; i < sp.size(); i++) p.host_descs[i].seed = 12345u + (uint32_t)i;
                 if (upload_descs(p.d_descs, p.host_descs, st) != hipSuccess ||
-                    launch_init(p.prec, 1, p.grid_link(), st) != hipSuccess) {
+                    launch_init(p.prec, 0, p.grid_link(), st) != hipSuccess) {
                     rc = fail(SU3_ERR_HIP, "autotune init failed");
                     break;
                 }
             }
             k_set_u64<<<1, 1, 0, st>>>(p.d_sweep, 0);
-            SweepOpts o{ 1, 1, 64, 0, 0, false };
+            SweepOpts o{ 4, 1, 64, 0, 0, false };
             rc = enqueue_sweeps(p, 1, o, st, nullptr);  // warm-up
             if (rc) break;
             hipEventRecord(e0, st);
@@ -526,6 +589,7 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
             }
             float ms = 0;
             hipEventElapsedTime(&ms, e0, e1);
+            if (ci == 0) t_default = ms;
             if (ms < best) {
                 best = ms;
                 bestc = cand[ci];
@@ -538,6 +602,7 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     if (rc) return rc;
+    if (best > 0.985f * t_default) bestc = default_cfg();
     std::lock_guard<std::mutex> lk(g_mu);
     g_tuned[shape_key(fs)] = bestc;
     return SU3_OK;
@@ -903,7 +968,8 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
     const LaunchCfg cfg = launch_choice(v);
     std::string key = std::to_string(n_sweeps) + "|" + std::to_string(o.n_or) + "," + std::to_string(o.n_hits) +
                       "," + std::to_string(o.max_tries) + "," + std::to_string(o.reunit_every) + "," +
-                      std::to_string(o.sampler) + "," + std::to_string(o.record) + "|" + cfg.str() + "|";
+                      std::to_string(o.sampler) + "," + std::to_string(o.record) + "|" + cfg.str() + "|" +
+                      std::to_string(g_group_bytes) + "|";
     for (auto* f : v) {
         char buf[64];
         snprintf(buf, sizeof buf, "%p,", (void*)f);
@@ -1310,6 +1376,13 @@ int32_t su3_set_launch(int32_t block, int32_t xcd_remap)
     std::lock_guard<std::mutex> lk(g_mu);
     g_forced_block = block;
     g_forced_remap = xcd_remap;
+    return SU3_OK;
+}
+
+int32_t su3_set_group_bytes(uint64_t bytes)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_group_bytes = (size_t)bytes;
     return SU3_OK;
 }
 

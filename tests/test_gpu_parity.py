@@ -206,11 +206,16 @@ def test_launch_shape_and_resume_invariance(m, orc):
 
 def test_batch_equals_separate_calls(m, orc):
     """One batched graph launch over lattices of uneven shapes gives bitwise
-    the fields and plaquettes of separate calls; replaying the cached graph
-    continues the chain."""
+    the fields and plaquettes of separate calls, for any grouping of the
+    lattices in the sweep schedule; replaying the cached graph continues the
+    chain."""
     shapes = [[4, 4, 4, 4], [6, 4, 2, 4], [8, 2, 4, 6]]
     betas = [5.9, 6.05, 6.2]
-    for prec in ("fp64", "fp32_r12"):
+    # group budget: one group, one lattice per group, the first two together
+    budgets = [224 << 20, 1, 2 * 4 * 256 * 144 + 4 * 192 * 144]
+    for prec, gbytes in (("fp64", budgets[0]), ("fp32_r12", budgets[0]), ("fp64", budgets[1]),
+                         ("fp32_r12", budgets[1]), ("fp64", budgets[2])):
+        m.su3_set_group_bytes(gbytes)
         fs = [field(m, d, prec) for d in shapes]
         gs = [field(m, d, prec) for d in shapes]
         for i, (a, b) in enumerate(zip(fs, gs)):
@@ -223,6 +228,7 @@ def test_batch_equals_separate_calls(m, orc):
                 assert np.array_equal(h, pb[:, i])
         for a, b in zip(fs, gs):
             assert np.array_equal(m.su3_field_to_host(a), m.su3_field_to_host(b))
+    m.su3_set_group_bytes(224 << 20)
     # and the FP64 member matches the oracle
     d = shapes[1]
     U = orc.init_hot(d, 11, 1)
