@@ -221,10 +221,13 @@ int32_t su3_set_tile(int32_t ty, int32_t tz, int32_t tt);
 int32_t su3_get_config(const su3_field* fs, int32_t n, int32_t out[5]);
 
 /* Kernel timing with HIP events recorded on the field's stream around each
- * phase launch.  While enabled, su3_batch_sweep_hb_or launches the same
- * kernels eagerly instead of replaying its graph.  kind 0 = heat-bath
- * phases, 1 = overrelaxation phases, 2 = the per-sweep plaquette kernel.
- * Enabling resets the accumulators. */
+ * run of consecutive launches of one kind (the 8 heat-bath phases of a
+ * lattice group, its 8 n_or overrelaxation phases, the plaquette kernel);
+ * su3_profile_read returns the summed time and the number of launches.
+ * While enabled, su3_batch_sweep_hb_or launches the same kernels eagerly
+ * instead of replaying its graph.  kind 0 = heat-bath phases,
+ * 1 = overrelaxation phases, 2 = the per-sweep plaquette kernel.  Enabling
+ * resets the accumulators. */
 int32_t su3_profile_enable(int32_t enable);
 int32_t su3_profile_read(int32_t kind, double* total_ms, int64_t* launches);
 

@@ -445,9 +445,16 @@ struct SweepOpts {
     bool record;
 };
 
-// Records HIP events around one launch when profiling.
+// Profiling: HIP events around a run of consecutive launches of one kind
+// (the heat-bath pass, the overrelaxation passes of a lattice group, the
+// plaquette), so that the average per launch carries no per-launch event
+// overhead.
+struct ProfRun {
+    int ev, kind, count;
+};
+
 struct ProfMark {
-    std::vector<std::pair<int, int>>* marks;
+    std::vector<ProfRun>* marks;
     hipStream_t st;
     int ev = -1;
     int32_t begin()
@@ -459,17 +466,29 @@ struct ProfMark {
         HIPCHK(hipEventRecord(g_events[ev], st));
         return SU3_OK;
     }
-    int32_t end(int kind)
+    int32_t end(int kind, int count)
     {
         if (!marks) return SU3_OK;
         HIPCHK(hipEventRecord(g_events[ev + 1], st));
-        marks->push_back({ ev, kind });
+        marks->push_back({ ev, kind, count });
         return SU3_OK;
     }
 };
 
+static int32_t read_marks(const std::vector<ProfRun>& marks)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& m : marks) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, g_events[m.ev], g_events[m.ev + 1]));
+        g_prof_ms[m.kind] += ms;
+        g_prof_n[m.kind] += m.count;
+    }
+    return SU3_OK;
+}
+
 static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, hipStream_t st,
-                              std::vector<std::pair<int, int>>* prof_marks)
+                              std::vector<ProfRun>* prof_marks)
 {
     const HbArgs hb{ o.n_hits, o.max_tries, o.sampler };
     const int ng = p.ngroups();
@@ -479,16 +498,16 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
         // next group starts, so its links stay cached between phases.
         for (int grp = 0; grp < ng; grp++) {
             const Grid gph = ng > 1 ? p.grid_phase_group(grp) : p.grid_phase();
+            ProfMark pm{ prof_marks, st };
             for (int pass = 0; pass <= o.n_or; pass++) {
                 const int kind = pass == 0 ? 0 : 1;
+                if (pass <= 1 && (rc = pm.begin())) return rc;
                 for (int mu = 0; mu < 4; mu++)
-                    for (int par = 0; par < 2; par++) {
-                        ProfMark pm{ prof_marks, st };
-                        if ((rc = pm.begin())) return rc;
+                    for (int par = 0; par < 2; par++)
                         HIPCHK(launch_phase(p.prec, kind, gph, mu, par, p.d_sweep, k, hb,
                                             kind == 0 ? p.d_exh : nullptr, st));
-                        if ((rc = pm.end(kind))) return rc;
-                    }
+                if (pass == 0 && (rc = pm.end(0, 8))) return rc;
+                if (pass == o.n_or && pass > 0 && (rc = pm.end(1, 8 * o.n_or))) return rc;
             }
         }
         if (o.reunit_every > 0) HIPCHK(launch_reunit(p.prec, p.grid_link(), p.d_sweep, k, o.reunit_every, st));
@@ -496,7 +515,7 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
             ProfMark pm{ prof_marks, st };
             if ((rc = pm.begin())) return rc;
             HIPCHK(launch_plaq_partial(p.prec, p.grid_site(), p.d_partials, st));
-            if ((rc = pm.end(2))) return rc;
+            if ((rc = pm.end(2, 1))) return rc;
             HIPCHK(launch_reduce_final(p.grid_site(), p.d_partials, p.d_out, 1, k * p.nlat, st));
         }
     }
@@ -909,7 +928,7 @@ int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattic
     k_set_u64<<<1, 1, 0, f->stream>>>(p.d_sweep, first_sweep);
     k_set_u64<<<1, 1, 0, f->stream>>>((uint64_t*)p.d_exh, 0);
     HIPCHK(hipGetLastError());
-    std::vector<std::pair<int, int>> marks;
+    std::vector<ProfRun> marks;
     const bool prof = g_profile;
     if ((rc = enqueue_sweeps(p, n_sweeps, o, f->stream, prof ? &marks : nullptr))) return rc;
     unsigned long long ex = 0;
@@ -922,15 +941,7 @@ int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattic
     HIPCHK(hipStreamSynchronize(f->stream));
     f->last_exhausted = (int64_t)ex;
     for (int k = 0; k < (int)h.size(); k++) plaq_hist[k] = 1.0 - h[k] / (6.0 * f->V);
-    if (prof) {
-        std::lock_guard<std::mutex> lk(g_mu);
-        for (auto& m : marks) {
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, g_events[m.first], g_events[m.first + 1]));
-            g_prof_ms[m.second] += ms;
-            g_prof_n[m.second] += 1;
-        }
-    }
+    if (prof && (rc = read_marks(marks))) return rc;
     return SU3_OK;
 }
 
@@ -1040,7 +1051,7 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
     k_set_u64<<<1, 1, 0, st>>>(p.d_sweep, first_sweep);
     k_set_u64<<<1, 1, 0, st>>>((uint64_t*)p.d_exh, 0);
     HIPCHK(hipGetLastError());
-    std::vector<std::pair<int, int>> marks;
+    std::vector<ProfRun> marks;
     if (prof) {
         if ((rc = enqueue_sweeps(p, n_sweeps, o, st, &marks))) return rc;
     } else {
@@ -1059,15 +1070,7 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
     if (o.record)
         for (int k = 0; k < n_sweeps; k++)
             for (int i = 0; i < n; i++) plaq_out[(size_t)k * n + i] = 1.0 - h[(size_t)k * n + i] / (6.0 * v[i]->V);
-    if (prof) {
-        std::lock_guard<std::mutex> lk(g_mu);
-        for (auto& mk : marks) {
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, g_events[mk.first], g_events[mk.first + 1]));
-            g_prof_ms[mk.second] += ms;
-            g_prof_n[mk.second] += 1;
-        }
-    }
+    if (prof && (rc = read_marks(marks))) return rc;
     return SU3_OK;
 }
 
