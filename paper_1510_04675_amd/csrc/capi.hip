@@ -1,6 +1,6 @@
 // capi.hip -- host side of the C ABI declared in include/msmc.h: argument
 // validation, field memory, descriptor tables, the sweep / HMC / flow /
-// prolongation drivers, HIP graph capture of batched sweeps, the launch-shape
+// prolongation host loop, HIP graph capture of batched sweeps, the launch-shape
 // autotuner and kernel timing.
 #include <hip/hip_runtime.h>
 
