@@ -14,10 +14,9 @@
  * i = n0 + L0*(n1 + L1*(n2 + L2*n3)) with n0 fastest, then direction mu,
  * then the 3x3 matrix row-major, then (re, im).
  *
- * Parity notes: functions whose result has no independent check are marked
- * "parity unpinned" in their comment.  Everything else is pinned by the
- * tests under tests/ against closed forms, invariants, brute force or an
- * independent library.
+ * Parity notes: every function is pinned by the tests under tests/ against
+ * closed forms, invariants, brute force or an independent library; one with
+ * no such check would say "parity unpinned" in its comment.
  */
 #include <complex.h>
 #include <math.h>
@@ -1123,7 +1122,8 @@ double orc_topological_charge(const int32_t L[4], const double* U)
 }
 
 /* Clover energy density summed over sites: E = -(1/2) sum_{mu,nu} Tr(F F)
- * per site, averaged over the volume.  Parity unpinned beyond invariances. */
+ * per site, averaged over the volume.  Pinned by the closed form on constant
+ * abelian flux fields and by gauge invariance. */
 double orc_clover_energy(const int32_t L[4], const double* U)
 {
     geom g = mkgeom(L);

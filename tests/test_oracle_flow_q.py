@@ -127,6 +127,27 @@ def test_q_constant_flux_closed_form(orc, H01, H23):
     assert abs(np.prod(big) / (2 * np.pi**2) * np.sum(fb * gb) - integer) < 1e-3 * max(1, abs(integer))
 
 
+@pytest.mark.parametrize("H01,H23", [((1, -1, 0), (1, 0, -1)), ((1, 1, -2), (0, 1, -1))])
+def test_clover_energy_constant_flux_closed_form(orc, H01, H23):
+    """Clover energy density on constant diagonal flux: F_01 = i diag(f),
+    f = sin(phi01 H01) minus its mean, likewise F_23 = i diag(g), all other
+    planes zero, so -sum_{mu<nu} Re Tr(F F) per site = sum f^2 + sum g^2."""
+    d = [8, 8, 6, 6]
+    U, p01, p23 = _flux_field(d, 1, 1, H01, H23)
+    f = np.sin(p01 * np.array(H01, float))
+    f -= f.mean()
+    g = np.sin(p23 * np.array(H23, float))
+    g -= g.mean()
+    exact = float(np.sum(f * f) + np.sum(g * g))
+    e = orc.clover_energy(d, U)
+    assert abs(e - exact) < 1e-13, (e, exact)
+    # doubling the flux quantum changes the energy as the closed form says
+    U2, q01, q23 = _flux_field(d, 2, 1, H01, H23)
+    f2 = np.sin(q01 * np.array(H01, float))
+    f2 -= f2.mean()
+    assert abs(orc.clover_energy(d, U2) - float(np.sum(f2 * f2) + np.sum(g * g))) < 1e-13
+
+
 def test_q_vanishes_on_pure_gauge_and_is_parity_odd(orc):
     d = [4, 4, 4, 4]
     U = orc.init_cold(d)
