@@ -173,6 +173,23 @@ int32_t su3_topological_charge(su3_field f, double* Q);
 /* Clover energy density (1/V) sum_x sum_{mu<nu} -Re Tr(F_munu F_munu). */
 int32_t su3_clover_energy(su3_field f, double* E);
 
+/* Wilson loops (Sec. III, the m x n loop, its plane/site average and the
+ * partial averages).  W_munu^{m x n}(n) = (1/3) Re Tr L_mu^m(n)
+ * L_nu^n(n + m e_mu) L_mu^m(n + n e_nu)^+ L_nu^n(n)^+ with L_mu^m the product
+ * of m links along mu, for mu < nu (m steps along the lower direction).
+ *   su3_wilson_loop: the average over all sites and the 6 planes,
+ *     1 <= m, n <= 1024 (su3_wilson_loop(f, 1, 1) is the plaquette);
+ *   su3_partial_plaquettes: out[d], d = 0, 1, 2, the average of the 1 x 1
+ *     loops with chi_munu(n) = d, chi_munu counting the odd coordinates of n
+ *     other than n_mu, n_nu (the partial average of Sec. III);
+ *   su3_displaced_loops: out[d], d = 0..4, the average of the 2 x 2 loops
+ *     from sites with chi(n) = d odd coordinates (after prolongation out[0]
+ *     equals the coarse plaquette).
+ * Computed in fp64 from the stored links, summed in a fixed order. */
+int32_t su3_wilson_loop(su3_field f, int32_t m, int32_t n, double* out);
+int32_t su3_partial_plaquettes(su3_field f, double out[3]);
+int32_t su3_displaced_loops(su3_field f, double out[5]);
+
 /* Reunitarize every link (Gram-Schmidt of rows 0,1 in fp64). */
 int32_t su3_reunitarize(su3_field f);
 

@@ -66,6 +66,9 @@ SIGNATURES = {
     "su3_profile_enable": (_i32, [_i32]),
     "su3_profile_read": (_i32, [_i32, C.POINTER(_d), C.POINTER(_i64)]),
     "su3_set_group_bytes": (_i32, [C.c_uint64]),
+    "su3_wilson_loop": (_i32, [_p, _i32, _i32, C.POINTER(_d)]),
+    "su3_partial_plaquettes": (_i32, [_p, C.c_void_p]),
+    "su3_displaced_loops": (_i32, [_p, C.c_void_p]),
     "su3_last_error": (C.c_char_p, []),
 }
 
@@ -262,6 +265,24 @@ def su3_clover_energy(f: Field) -> float:
     out = C.c_double()
     _ck(lib().su3_clover_energy(f.handle, C.byref(out)))
     return out.value
+
+
+def su3_wilson_loop(f: Field, m: int, n: int) -> float:
+    out = C.c_double()
+    _ck(lib().su3_wilson_loop(f.handle, m, n, C.byref(out)))
+    return out.value
+
+
+def su3_partial_plaquettes(f: Field) -> np.ndarray:
+    out = np.zeros(3)
+    _ck(lib().su3_partial_plaquettes(f.handle, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def su3_displaced_loops(f: Field) -> np.ndarray:
+    out = np.zeros(5)
+    _ck(lib().su3_displaced_loops(f.handle, out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def su3_reunitarize(f: Field):

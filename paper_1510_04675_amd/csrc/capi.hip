@@ -354,7 +354,8 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
         HIPCHK(hipMalloc(&p.d_bbeg_site, sizeof(int) * (p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_bbeg_lw, sizeof(int) * (p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_bbeg_grp, sizeof(int) * (2 * p.nlat + 1)));
-        HIPCHK(hipMalloc(&p.d_partials, sizeof(double) * std::max(p.nblk_site, p.nblk_link)));
+        // up to 5 classes of site partials (Wilson loop classes) or one per link block
+        HIPCHK(hipMalloc(&p.d_partials, sizeof(double) * std::max(5 * p.nblk_site, p.nblk_link)));
         HIPCHK(hipMalloc(&p.d_sweep, sizeof(uint64_t)));
         HIPCHK(hipMalloc(&p.d_exh, sizeof(unsigned long long)));
     }
@@ -1138,6 +1139,61 @@ int32_t su3_clover_energy(su3_field f, double* E)
     rc = scalar_reduction(f, 1, E);
     if (!rc) *E /= f->V;
     return rc;
+}
+
+// Class sums of Wilson loops (mode 0: all, 1: chi_munu, 2: chi), each class
+// divided by its number of loops; extents are even, so a given pattern of odd
+// coordinates holds exactly V / 16 sites.
+static int32_t loop_classes(su3_field f, int m, int n, int mode, double* out)
+{
+    int32_t rc = single_plan(f, 5);
+    if (rc) return rc;
+    Plan& p = f->plan;
+    const Grid g = p.grid_site();
+    HIPCHK(launch_loops_partial(f->prec, g, m, n, mode, p.d_partials, f->stream));
+    const int nclass = mode == 0 ? 1 : (mode == 1 ? 3 : 5);
+    for (int c = 0; c < nclass; c++)
+        HIPCHK(launch_reduce_final(g, p.d_partials + (size_t)c * p.nblk_site, p.d_out, 1, c, f->stream));
+    double r[5];
+    HIPCHK(hipMemcpyAsync(r, p.d_out, sizeof(double) * nclass, hipMemcpyDeviceToHost, f->stream));
+    HIPCHK(hipStreamSynchronize(f->stream));
+    static const double binom2[3] = { 1, 2, 1 }, binom4[5] = { 1, 4, 6, 4, 1 };
+    for (int c = 0; c < nclass; c++) {
+        double cnt;
+        if (mode == 0)
+            cnt = 6.0 * f->V;
+        else if (mode == 1)
+            cnt = 6.0 * binom2[c] * (f->V / 4.0);  // chi_munu sees the parities of 2 coordinates
+        else
+            cnt = 6.0 * binom4[c] * (f->V / 16.0);
+        out[c] = r[c] / cnt;
+    }
+    return SU3_OK;
+}
+
+int32_t su3_wilson_loop(su3_field f, int32_t m, int32_t n, double* out)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!out) return fail(SU3_ERR_ARG, "out is NULL");
+    if (m < 1 || n < 1 || m > 1024 || n > 1024) return fail(SU3_ERR_ARG, "loop extents must be in [1, 1024]");
+    return loop_classes(f, m, n, 0, out);
+}
+
+int32_t su3_partial_plaquettes(su3_field f, double out[3])
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!out) return fail(SU3_ERR_ARG, "out is NULL");
+    return loop_classes(f, 1, 1, 1, out);
+}
+
+int32_t su3_displaced_loops(su3_field f, double out[5])
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!out) return fail(SU3_ERR_ARG, "out is NULL");
+    return loop_classes(f, 2, 2, 2, out);
 }
 
 int32_t su3_reunitarize(su3_field f)

@@ -304,6 +304,64 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_energy(Gr
     if (threadIdx.x == 0) partials[s.lb] = acc;
 }
 
+// Wilson loops (Sec. III, loop and partial-average equations).  For every
+// site n and plane mu < nu the m x n loop
+//   W = (1/3) Re Tr L_mu^m(n) L_nu^n(n + m mu) L_mu^m(n + n nu)^+ L_nu^n(n)^+,
+// L_mu^m(n) the product of m links along mu, is added to a class:
+//   mode 0: one class (all loops);
+//   mode 1: class chi_munu(n) in 0..2, the number of odd coordinates of n
+//           other than n_mu, n_nu (partially averaged plaquettes, m = n = 1);
+//   mode 2: class chi(n) in 0..4, the number of odd coordinates of n
+//           (displaced loops, m = n = 2).
+// Block partials of class c go to partials[c * nblocks + logical block].
+template <typename R, int NC>
+__global__ void __launch_bounds__(256) k_loops(Grid gr, int lm, int ln, int mode, double* __restrict__ partials)
+{
+    const SiteIdx s = site_index(gr);
+    double acc[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 };
+    if (s.valid) {
+        const LatDesc& d = gr.descs[s.l];
+        const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
+        const int odd[4] = { s.n[0] & 1, s.n[1] & 1, s.n[2] & 1, s.n[3] & 1 };
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++)
+#pragma unroll
+            for (int nu = mu + 1; nu < 4; nu++) {
+                int x[4] = { s.n[0], s.n[1], s.n[2], s.n[3] };
+                M3<double> P = ld_d(U, d.g, mu, x);
+                x[mu] = wrap_add(x[mu], 1, d.g.L[mu]);
+                for (int a = 1; a < lm; a++) {
+                    P = m_mul(P, ld_d(U, d.g, mu, x));
+                    x[mu] = wrap_add(x[mu], 1, d.g.L[mu]);
+                }
+                for (int b = 0; b < ln; b++) {
+                    P = m_mul(P, ld_d(U, d.g, nu, x));
+                    x[nu] = wrap_add(x[nu], 1, d.g.L[nu]);
+                }
+                for (int a = 0; a < lm; a++) {
+                    x[mu] = wrap_add(x[mu], -1, d.g.L[mu]);
+                    P = m_mul_nd(P, ld_d(U, d.g, mu, x));
+                }
+                for (int b = 0; b < ln; b++) {
+                    x[nu] = wrap_add(x[nu], -1, d.g.L[nu]);
+                    P = m_mul_nd(P, ld_d(U, d.g, nu, x));
+                }
+                const double w = (P.re[0] + P.re[4] + P.re[8]) / 3.0;
+                const int all = odd[0] + odd[1] + odd[2] + odd[3];
+                const int c = mode == 0 ? 0 : (mode == 1 ? all - odd[mu] - odd[nu] : all);
+#pragma unroll
+                for (int k = 0; k < 5; k++)
+                    if (k == c) acc[k] += w;
+            }
+    }
+    const int nclass = mode == 0 ? 1 : (mode == 1 ? 3 : 5);
+    for (int k = 0; k < nclass; k++) {
+        const double v = block_sum_256(acc[k]);
+        if (threadIdx.x == 0) partials[(size_t)k * gr.nblocks + s.lb] = v;
+        __syncthreads();  // the next block sum reuses the shared slots
+    }
+}
+
 // One block per lattice: out[l * stride + off] = sum of its partials.
 __global__ void __launch_bounds__(256) k_reduce_final(const int* __restrict__ bbeg, const double* __restrict__ partials,
                                                       double* __restrict__ out, int stride, int off)
@@ -342,6 +400,13 @@ hipError_t launch_energy_partial(int prec, const Grid& gr, double* partials, hip
 {
     if (gr.nblocks <= 0) return hipSuccess;
     DISPATCH_PREC_M(prec, (k_energy<R, NC><<<gr.nblocks, 256, 0, st>>>(gr, partials)));
+    return hipGetLastError();
+}
+
+hipError_t launch_loops_partial(int prec, const Grid& gr, int m, int n, int mode, double* partials, hipStream_t st)
+{
+    if (gr.nblocks <= 0) return hipSuccess;
+    DISPATCH_PREC_M(prec, (k_loops<R, NC><<<gr.nblocks, 256, 0, st>>>(gr, m, n, mode, partials)));
     return hipGetLastError();
 }
 

@@ -121,6 +121,9 @@ hipError_t launch_plaq_partial(int prec, const Grid& gr, double* partials, hipSt
 hipError_t launch_reduce_final(const Grid& gr, const double* partials, double* out, int stride, int off,
                                hipStream_t st);
 // Clover topological charge density summed per block (fp64).
+// Wilson loop sums by class (mode 0: all; 1: chi_munu, 3 classes; 2: chi,
+// 5 classes); partials hold nclass x nblocks doubles.
+hipError_t launch_loops_partial(int prec, const Grid& gr, int m, int n, int mode, double* partials, hipStream_t st);
 hipError_t launch_qtop_partial(int prec, const Grid& gr, double* partials, hipStream_t st);
 // Clover energy density summed per block (fp64).
 hipError_t launch_energy_partial(int prec, const Grid& gr, double* partials, hipStream_t st);

@@ -122,12 +122,30 @@ def test_config3_multiscale_step(m, orc):
     print(f"\nC3 prolongation: iterations {list(it)} (oracle {list(rit)}), max link diff {dpro:.1e}")
     assert list(it) == list(rit)
     assert dpro < 1e-11
+    # partial and displaced averages after prolongation (Sec. III): the displaced
+    # 2 x 2 loops from even sites are the coarse plaquettes
+    sync()
+    t0 = time.perf_counter()
+    dl = m.su3_displaced_loops(f64)
+    pp = m.su3_partial_plaquettes(f64)
+    times["displaced + partial averages (fp64)"] = time.perf_counter() - t0
+    print(f"C3 after prolongation: displaced 2x2 {np.round(dl, 6).tolist()}, partial 1x1 {np.round(pp, 6).tolist()}, "
+          f"coarse plaquette {hcref[-1]:.6f}")
+    assert abs(dl[0] - hcref[-1]) < 1e-13
+    for k in range(5):
+        assert abs(dl[k] - orc.displaced_2x2(df, Uf, k)) < 1e-13
+    for k in range(3):
+        assert abs(pp[k] - orc.partial_plaquette(df, Uf, k)) < 1e-13
 
     fr = m.Field(df, "fp32_r12")
     m.su3_prolongate(c, fr, 0.05, 1e-5, 10000)
     t0 = time.perf_counter()
     hr = m.su3_sweep_hb_or(fr, 6.0, 7, 0, 100, 50, P(reunit=10))
     times["rethermalization 50 sweeps (r12)"] = time.perf_counter() - t0
+    dl_after = m.su3_displaced_loops(fr)
+    print(f"C3 after rethermalization: displaced 2x2 {np.round(dl_after, 5).tolist()} (spread "
+          f"{dl_after.max() - dl_after.min():.1e}, before {dl.max() - dl.min():.1e})")
+    assert dl_after.max() - dl_after.min() < 0.2 * (dl.max() - dl.min())
     href, _ = orc.sweep_hb_or(df, Uf, 6.0, 7, 0, 100, 50)
     spread = float(np.std(href[25:]))
     print(f"C3 rethermalization: first sweep dP {abs(hr[0] - href[0]):.1e}; <P>[25:50] r12 {hr[25:].mean():.6f} "

@@ -92,6 +92,32 @@ def test_reduced_precision_plaquette_of_the_same_field(m, orc, prec):
     assert abs(p - pref) < 1e-7
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_r12"])
+def test_wilson_loops_match_oracle(m, orc, prec):
+    """m x n loops, partially averaged plaquettes (by chi_munu) and
+    displaced 2 x 2 loops (by chi) against the oracle on the stored links of
+    a smoothed ragged field; 1 x 1 equals the plaquette."""
+    d = [6, 4, 8, 10]
+    U = si.random_field(d, 21)
+    orc.wilson_flow(d, U, 0.03, 4)
+    f = field(m, d, prec)
+    m.su3_field_from_host(f, U)
+    Uh = m.su3_field_to_host(f)
+    tol = 1e-13 if prec == "fp64" else 1e-7
+    assert abs(m.su3_wilson_loop(f, 1, 1) - orc.plaquette(d, Uh)) < tol
+    for a, b in ((1, 2), (2, 1), (2, 3), (3, 3)):
+        assert abs(m.su3_wilson_loop(f, a, b) - orc.wilson_loop(d, Uh, a, b)) < tol, (a, b)
+    pp = m.su3_partial_plaquettes(f)
+    dl = m.su3_displaced_loops(f)
+    for k in range(3):
+        assert abs(pp[k] - orc.partial_plaquette(d, Uh, k)) < tol, k
+    for k in range(5):
+        assert abs(dl[k] - orc.displaced_2x2(d, Uh, k)) < tol, k
+    # the class averages recombine to the full averages
+    assert abs((pp[0] + 2 * pp[1] + pp[2]) / 4 - m.su3_wilson_loop(f, 1, 1)) < tol
+    assert abs(np.dot([1, 4, 6, 4, 1], dl) / 16 - m.su3_wilson_loop(f, 2, 2)) < tol
+
+
 def test_gauge_transform_matches_oracle(m, orc):
     d = [4, 4, 2, 4]
     U = si.random_field(d, 8)
