@@ -139,6 +139,49 @@ def run_hmc(m, torch, dims, n_traj=20, n_steps=40, beta=6.0, therm=200, prec="fp
     return out
 
 
+def run_multiscale(m, torch, L=32, beta_c=5.7, beta=6.0, n_coarse=20, n_sweeps=20, every=4):
+    """One multiscale step at L^4: a coarse (L/2)^4 hot start (seed 11)
+    thermalized by n_coarse sweeps at beta_c, prolongated (c = 0.05,
+    tolerance 1e-5) in fp64, rounded to R12 and rethermalized at beta; reports
+    the stage times and the displaced 2x2 loops (their spread measures how far
+    translational symmetry is from restored)."""
+    c = m.Field([L // 2] * 4, "fp64")
+    m.su3_init_hot(c, 11, 0)
+    m.su3_sweep_hb_or(c, beta_c, 11, 0, 0, n_coarse, m.hb_params(n_or=4), record=False)
+    f64 = m.Field([L] * 4, "fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = m.su3_prolongate(c, f64, 0.05, 1e-5, 10000)
+    torch.cuda.synchronize()
+    t_pro = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dl = m.su3_displaced_loops(f64)
+    t_loops = time.perf_counter() - t0
+    f = m.Field([L] * 4, "fp32_r12")
+    m.su3_field_copy(f, f64)
+    f64.close()
+    c.close()
+    curve = [[0, float(dl.max() - dl.min())]]
+    t_sw = 0.0
+    for k in range(0, n_sweeps, every):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.su3_sweep_hb_or(f, beta, 11, 0, 1000 + k, every, m.hb_params(n_or=4, reunit_every=10), record=False)
+        torch.cuda.synchronize()
+        t_sw += time.perf_counter() - t0
+        d = m.su3_displaced_loops(f)
+        curve.append([k + every, float(d.max() - d.min())])
+    out = {"coarse": f"{L // 2}^4 hot start (seed 11), {n_coarse} sweeps at beta {beta_c}",
+           "fine": f"{L}^4, R12 rethermalization at beta {beta}",
+           "prolongation_ms": round(1e3 * t_pro, 2), "ape_steps_per_stage": [int(x) for x in iters],
+           "displaced_loops_ms": round(1e3 * t_loops, 3),
+           "displaced_2x2_after_prolongation": [round(float(x), 6) for x in dl],
+           "displaced_spread_vs_sweeps": curve,
+           "rethermalization_sweeps_per_s": round(n_sweeps / t_sw, 1)}
+    f.close()
+    return out
+
+
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
@@ -215,10 +258,11 @@ def main():
     ap.add_argument("--lattice", type=int, default=32)
     ap.add_argument("--batch", type=int, default=4, help="lattices in the FP32 batched run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of parts to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch,hmc)")
+    ap.add_argument("--only", default="", help="comma list of parts to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch,hmc,multiscale)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-hmc", action="store_true", help="skip the HMC report")
+    ap.add_argument("--no-multiscale", action="store_true", help="skip the prolongation / displaced-loop report")
     ap.add_argument("--launch", default="", help="fix the launch shape block,xcd_remap,ty,tz,tt (implies --no-tune)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -259,8 +303,13 @@ def main():
         log("bench: hmc (32^4, tau 1, 40 steps, 20 trajectories) ...")
         hmc = run_hmc(m, torch, dims)
         log(f"bench: hmc {hmc['trajectories_per_s']} traj/s, acceptance {hmc['acceptance']}")
-    if head is None:  # only the HMC part was asked for
-        print(json.dumps({"hmc": hmc}), flush=True)
+    ms = None
+    if not a.no_multiscale and (not a.only or "multiscale" in want):
+        log("bench: multiscale (16^4 -> 32^4 prolongation, displaced loops) ...")
+        ms = run_multiscale(m, torch, L)
+        log(f"bench: prolongation {ms['prolongation_ms']} ms, displaced spread {ms['displaced_spread_vs_sweeps']}")
+    if head is None:  # only the HMC / multiscale parts were asked for
+        print(json.dumps({"hmc": hmc, "multiscale": ms}), flush=True)
         return
     cpu = None
     if not a.no_cpu_baseline:
@@ -298,6 +347,8 @@ def main():
     }
     if hmc is not None:
         line["hmc"] = hmc
+    if ms is not None:
+        line["multiscale"] = ms
     if "fp64" in res:
         # every variant's lattice 0 starts from the same hot start and draws the
         # same uniforms, so its first sweep is comparable with the fp64 one
