@@ -166,6 +166,33 @@ int32_t su3_action(su3_field f, double beta, double* out);
  * place, in the storage precision (Sec. IV.B). */
 int32_t su3_wilson_flow(su3_field f, double eps, int32_t n_steps);
 
+/* Adaptive-step Wilson flow (Sec. IV.B: the adaptive integrator with a
+ * tolerance and a maximum step; the paper's runs use tol = 0.01,
+ * max_step = 0.2).  Each step of size h is the RK3 step of su3_wilson_flow;
+ * its error estimate is d = max over links and matrix elements of
+ * |W3 - W~|, W~ = exp(2 Z1 - Z0) W0 the embedded second-order result.
+ * d <= tol accepts the step, otherwise the field returns to W0; the next
+ * size is min(max_step, 0.95 h (tol/d)^(1/3)), starting from eps0.  Steps
+ * are shortened to land exactly on each of the n_meas ascending times
+ * t_meas[k] in [0, t_end], where E_out[k] (clover energy density,
+ * su3_clover_energy) and Q_out[k] (clover charge) are recorded.  The field
+ * is flowed in place to t_end.  n_accepted / n_rejected (may be NULL)
+ * receive the step counts.  SU3_ERR_NUMERIC if the step size collapses.
+ * Allocates three link-sized scratch fields on first use. */
+int32_t su3_wilson_flow_adaptive(su3_field f, double t_end, double tol, double max_step, double eps0,
+                                 const double* t_meas, int32_t n_meas, double* E_out, double* Q_out,
+                                 int32_t* n_accepted, int32_t* n_rejected);
+
+/* Flow scale (Sec. IV.B): the t where t^2 E(t) crosses `target` (0.3 for
+ * t0), linearly interpolated between the two bracketing points of the host
+ * arrays t[0..n), E[0..n).  SU3_ERR_NUMERIC if no pair brackets it. */
+int32_t su3_flow_t0(const double* t, const double* E, int32_t n, double target, double* t0);
+
+/* Admissibility measure (Sec. IV.D): h = max over plaquettes of
+ * s_p = 3 [1 - (1/3) Re Tr U_p]; fields with h < 0.067 fall into distinct
+ * topological sectors. */
+int32_t su3_max_plaquette_action(su3_field f, double* h);
+
 /* Clover topological charge: F_munu = traceless part of (Q_munu -
  * Q_munu^+)/8 with Q_munu the four-leaf clover, q(x) = -(1/(2 pi^2))
  * Re Tr[F01 F23 - F02 F13 + F03 F12], Q = sum_x q(x); fp64. */

@@ -79,6 +79,10 @@ def lib():
             "orc_wilson_flow": (None, [P, P, d, i32]),
             "orc_topological_charge": (d, [P, P]),
             "orc_clover_energy": (d, [P, P]),
+            "orc_wilson_flow_adaptive": (i32, [P, P, d, d, d, d, P, i32, P, P, P, P]),
+            "orc_flow_t0": (i32, [P, P, i32, d, P]),
+            "orc_max_splaq": (d, [P, P]),
+            "orc_flow_step_distance": (d, [P, P, d]),
             "orc_max_su3_dev": (d, [P, P]),
             "orc_set_threads": (None, [i32]),
             "orc_max_threads": (i32, []),
@@ -324,6 +328,43 @@ def topological_charge(dims, U) -> float:
 def clover_energy(dims, U) -> float:
     _chk(U, dims)
     return lib().orc_clover_energy(_ptr(_dims(dims)), _ptr(U))
+
+
+def wilson_flow_adaptive(dims, U, t_end, tol=0.01, max_step=0.2, eps0=0.01, t_meas=()):
+    """Adaptive-step RK3 flow of U (in place) to t_end; returns (E, Q, n_accepted,
+    n_rejected) with E, Q measured at the ascending times t_meas (<= t_end)."""
+    _chk(U, dims)
+    tm = np.ascontiguousarray(t_meas, dtype=np.float64)
+    if tm.size and (np.any(np.diff(tm) <= 0) or tm[-1] > t_end):
+        raise ValueError("measurement times must ascend and not exceed t_end")
+    E = np.full(tm.size, np.nan)
+    Q = np.full(tm.size, np.nan)
+    na, nr = C.c_int32(), C.c_int32()
+    rc = lib().orc_wilson_flow_adaptive(_ptr(_dims(dims)), _ptr(U), t_end, tol, max_step, eps0, _ptr(tm),
+                                        int(tm.size), _ptr(E), _ptr(Q), C.byref(na), C.byref(nr))
+    if rc != 0:
+        raise RuntimeError("adaptive flow did not converge")
+    return E, Q, na.value, nr.value
+
+
+def flow_step_distance(dims, U, h) -> float:
+    """One RK3 flow step of size h in place; returns the embedded error distance."""
+    _chk(U, dims)
+    return lib().orc_flow_step_distance(_ptr(_dims(dims)), _ptr(U), h)
+
+
+def flow_t0(t, E, target=0.3) -> float:
+    """The t where t^2 E(t) crosses target, linearly interpolated (NaN if not bracketed)."""
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    out = C.c_double()
+    rc = lib().orc_flow_t0(_ptr(t), _ptr(E), int(t.size), target, C.byref(out))
+    return out.value if rc == 0 else float("nan")
+
+
+def max_splaq(dims, U) -> float:
+    _chk(U, dims)
+    return lib().orc_max_splaq(_ptr(_dims(dims)), _ptr(U))
 
 
 def max_su3_dev(dims, U) -> float:

@@ -1085,6 +1085,152 @@ void orc_wilson_flow(const int32_t L[4], double* U, double eps, int32_t n_steps)
 }
 
 /* ------------------------------------------------------------------ */
+/* Adaptive-step flow.  Sec. IV.B uses the adaptive integrator of      */
+/* Fritzsch and Ramos with a tolerance and a maximum step; the error   */
+/* estimate and the step rule here are this implementation's reading:  */
+/* a step of size h is the RK3 step above, W3 its result; the embedded */
+/* second-order result is W~ = exp(2 Z1 - Z0) W0 (Z_i = h Z(W_i)), and  */
+/* d = max over links and matrix elements of |W3 - W~|.  d <= tol      */
+/* accepts the step; either way the next step size is                   */
+/* min(max_step, 0.95 h (tol / d)^(1/3)).  A step is shortened to land */
+/* on the next measurement time; at each measurement time the clover   */
+/* energy density E and charge Q are recorded.                          */
+/* ------------------------------------------------------------------ */
+double orc_clover_energy(const int32_t L[4], const double* U);
+double orc_topological_charge(const int32_t L[4], const double* U);
+
+static double flow_step_embedded(const geom* g, double* U, double* W0, mat3* Z0, mat3* Z1, mat3* Z2, double h)
+{
+    size_t nl = (size_t)g->V * 4;
+    memcpy(W0, U, sizeof(double) * (size_t)g->V * 72);
+    flow_Z(g, U, Z0, h);
+#pragma omp parallel for schedule(static)
+    for (size_t l = 0; l < nl; l++) {
+        mat3 m = m_mul(m_exp(m_scale(Z0[l], 0.25)), ld(U, (int64_t)(l / 4), (int)(l % 4)));
+        st(U, (int64_t)(l / 4), (int)(l % 4), &m);
+    }
+    flow_Z(g, U, Z1, h);
+#pragma omp parallel for schedule(static)
+    for (size_t l = 0; l < nl; l++) {
+        mat3 X = m_sub(m_scale(Z1[l], 8.0 / 9.0), m_scale(Z0[l], 17.0 / 36.0));
+        mat3 m = m_mul(m_exp(X), ld(U, (int64_t)(l / 4), (int)(l % 4)));
+        st(U, (int64_t)(l / 4), (int)(l % 4), &m);
+    }
+    flow_Z(g, U, Z2, h);
+    double* dl = (double*)malloc(sizeof(double) * nl);
+#pragma omp parallel for schedule(static)
+    for (size_t l = 0; l < nl; l++) {
+        int64_t i = (int64_t)(l / 4);
+        int mu = (int)(l % 4);
+        mat3 X = m_add(m_sub(m_scale(Z2[l], 0.75), m_scale(Z1[l], 8.0 / 9.0)), m_scale(Z0[l], 17.0 / 36.0));
+        mat3 w3 = m_mul(m_exp(X), ld(U, i, mu));
+        st(U, i, mu, &w3);
+        mat3 w2 = m_mul(m_exp(m_sub(m_scale(Z1[l], 2.0), Z0[l])), ld(W0, i, mu));
+        double worst = 0;
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) worst = fmax(worst, cabs(w3.e[r][c] - w2.e[r][c]));
+        dl[l] = worst;
+    }
+    double d = 0;
+    for (size_t l = 0; l < nl; l++) d = fmax(d, dl[l]);
+    free(dl);
+    return d;
+}
+
+int32_t orc_wilson_flow_adaptive(const int32_t L[4], double* U, double t_end, double tol, double max_step, double eps0,
+                                 const double* t_meas, int32_t n_meas, double* E_out, double* Q_out,
+                                 int32_t* n_accepted, int32_t* n_rejected)
+{
+    geom g = mkgeom(L);
+    size_t nl = (size_t)g.V * 4;
+    double* W0 = (double*)malloc(sizeof(double) * (size_t)g.V * 72);
+    mat3* Z0 = (mat3*)malloc(sizeof(mat3) * nl);
+    mat3* Z1 = (mat3*)malloc(sizeof(mat3) * nl);
+    mat3* Z2 = (mat3*)malloc(sizeof(mat3) * nl);
+    double t = 0, eps = fmin(eps0, max_step);
+    int32_t k = 0, acc = 0, rej = 0, rc = 0;
+    while (k < n_meas && t_meas[k] <= 0) {
+        E_out[k] = orc_clover_energy(L, U);
+        Q_out[k] = orc_topological_charge(L, U);
+        k++;
+    }
+    while (t < t_end) {
+        double target = (k < n_meas && t_meas[k] < t_end) ? t_meas[k] : t_end;
+        int lands = eps >= target - t;
+        double h = lands ? target - t : eps;
+        double d = flow_step_embedded(&g, U, W0, Z0, Z1, Z2, h);
+        if (d <= tol) {
+            acc++;
+            t = lands ? target : t + h;
+            while (k < n_meas && t_meas[k] <= t) {
+                E_out[k] = orc_clover_energy(L, U);
+                Q_out[k] = orc_topological_charge(L, U);
+                k++;
+            }
+        } else {
+            rej++;
+            memcpy(U, W0, sizeof(double) * (size_t)g.V * 72);
+        }
+        eps = d > 0 ? fmin(max_step, 0.95 * h * cbrt(tol / d)) : max_step;
+        if (rej > 100000 || !(eps > 1e-12)) {
+            rc = -1;
+            break;
+        }
+    }
+    if (n_accepted) *n_accepted = acc;
+    if (n_rejected) *n_rejected = rej;
+    free(W0);
+    free(Z0);
+    free(Z1);
+    free(Z2);
+    return rc;
+}
+
+/* One RK3 step of size h (U <- W3), returning its embedded-error distance d. */
+double orc_flow_step_distance(const int32_t L[4], double* U, double h)
+{
+    geom g = mkgeom(L);
+    size_t nl = (size_t)g.V * 4;
+    double* W0 = (double*)malloc(sizeof(double) * (size_t)g.V * 72);
+    mat3* Z0 = (mat3*)malloc(sizeof(mat3) * nl);
+    mat3* Z1 = (mat3*)malloc(sizeof(mat3) * nl);
+    mat3* Z2 = (mat3*)malloc(sizeof(mat3) * nl);
+    double d = flow_step_embedded(&g, U, W0, Z0, Z1, Z2, h);
+    free(W0);
+    free(Z0);
+    free(Z1);
+    free(Z2);
+    return d;
+}
+
+/* Flow scale: the t at which t^2 E(t) crosses `target` (0.3 for t0, Sec.  */
+/* IV.B), by linear interpolation between the two bracketing measurements. */
+/* Returns 0, or -1 when no measurement pair brackets the target.          */
+int32_t orc_flow_t0(const double* t, const double* E, int32_t n, double target, double* t0)
+{
+    for (int32_t k = 1; k < n; k++) {
+        double y0 = t[k - 1] * t[k - 1] * E[k - 1], y1 = t[k] * t[k] * E[k];
+        if (y0 < target && y1 >= target) {
+            *t0 = t[k - 1] + (target - y0) * (t[k] - t[k - 1]) / (y1 - y0);
+            return 0;
+        }
+    }
+    return -1;
+}
+
+/* Admissibility measure (Sec. IV.D): h = max over plaquettes of          */
+/* s_p = 3 [1 - (1/3) Re Tr U_p].                                        */
+double orc_max_splaq(const int32_t L[4], const double* U)
+{
+    geom g = mkgeom(L);
+    double h = 0;
+    for (int64_t i = 0; i < g.V; i++)
+        for (int mu = 0; mu < 4; mu++)
+            for (int nu = mu + 1; nu < 4; nu++) h = fmax(h, 3.0 - creal(m_tr(plaq_mat(&g, U, i, mu, nu))));
+    return h;
+}
+
+/* ------------------------------------------------------------------ */
 /* Clover field strength and topological charge (Sec. IV.D uses an      */
 /* improved definition; this is the clover one).                        */
 /* Q_munu(x) = sum of the four counter-clockwise leaves in the munu     */

@@ -69,6 +69,9 @@ SIGNATURES = {
     "su3_wilson_loop": (_i32, [_p, _i32, _i32, C.POINTER(_d)]),
     "su3_partial_plaquettes": (_i32, [_p, C.c_void_p]),
     "su3_displaced_loops": (_i32, [_p, C.c_void_p]),
+    "su3_wilson_flow_adaptive": (_i32, [_p, _d, _d, _d, _d, _p, _i32, _p, _p, C.POINTER(_i32), C.POINTER(_i32)]),
+    "su3_flow_t0": (_i32, [_p, _p, _i32, _d, C.POINTER(_d)]),
+    "su3_max_plaquette_action": (_i32, [_p, C.POINTER(_d)]),
     "su3_last_error": (C.c_char_p, []),
 }
 
@@ -253,6 +256,33 @@ def su3_action(f: Field, beta) -> float:
 
 def su3_wilson_flow(f: Field, eps, n_steps):
     _ck(lib().su3_wilson_flow(f.handle, eps, n_steps))
+
+
+def su3_wilson_flow_adaptive(f: Field, t_end, tol=0.01, max_step=0.2, eps0=0.01, t_meas=()):
+    """Returns (E, Q, n_accepted, n_rejected) at the measurement times."""
+    tm = np.ascontiguousarray(t_meas, dtype=np.float64)
+    E = np.zeros(tm.size)
+    Q = np.zeros(tm.size)
+    na, nr = C.c_int32(), C.c_int32()
+    _ck(lib().su3_wilson_flow_adaptive(f.handle, t_end, tol, max_step, eps0, tm.ctypes.data_as(C.c_void_p),
+                                       int(tm.size), E.ctypes.data_as(C.c_void_p), Q.ctypes.data_as(C.c_void_p),
+                                       C.byref(na), C.byref(nr)))
+    return E, Q, na.value, nr.value
+
+
+def su3_flow_t0(t, E, target=0.3) -> float:
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    out = C.c_double()
+    _ck(lib().su3_flow_t0(t.ctypes.data_as(C.c_void_p), E.ctypes.data_as(C.c_void_p), int(t.size), target,
+                          C.byref(out)))
+    return out.value
+
+
+def su3_max_plaquette_action(f: Field) -> float:
+    out = C.c_double()
+    _ck(lib().su3_max_plaquette_action(f.handle, C.byref(out)))
+    return out.value
 
 
 def su3_topological_charge(f: Field) -> float:

@@ -219,7 +219,7 @@ struct su3_field_s {
     bool owned = false;
     hipStream_t stream = nullptr;
     // scratch
-    void* alt[2] = { nullptr, nullptr };
+    void* alt[3] = { nullptr, nullptr, nullptr };
     void* aux8 = nullptr;
     LatDesc* d_extra = nullptr;  // 8 descriptor variants (HMC / flow ping-pong)
     Plan plan;                    // single-lattice tables
@@ -355,7 +355,7 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
         HIPCHK(hipMalloc(&p.d_bbeg_lw, sizeof(int) * (p.nlat + 1)));
         HIPCHK(hipMalloc(&p.d_bbeg_grp, sizeof(int) * (2 * p.nlat + 1)));
         // up to 5 classes of site partials (Wilson loop classes) or one per link block
-        HIPCHK(hipMalloc(&p.d_partials, sizeof(double) * std::max(5 * p.nblk_site, p.nblk_link)));
+        HIPCHK(hipMalloc(&p.d_partials, sizeof(double) * std::max({ 5 * p.nblk_site, p.nblk_link, p.nblk_lw })));
         HIPCHK(hipMalloc(&p.d_sweep, sizeof(uint64_t)));
         HIPCHK(hipMalloc(&p.d_exh, sizeof(unsigned long long)));
     }
@@ -702,10 +702,10 @@ static int32_t single_plan(su3_field_s* f, int out_cap)
     return SU3_OK;
 }
 
-static int32_t ensure_scratch(su3_field_s* f, bool alts, bool aux)
+static int32_t ensure_scratch(su3_field_s* f, bool alts, bool aux, int n_alts = 2)
 {
-    if (alts && !f->alt[1]) {
-        for (int k = 0; k < 2; k++)
+    if (alts) {
+        for (int k = 0; k < n_alts; k++)
             if (!f->alt[k] && hipMalloc(&f->alt[k], f->bytes) != hipSuccess)
                 return fail(SU3_ERR_NOMEM, "scratch field allocation failed");
     }
@@ -809,6 +809,7 @@ int32_t su3_field_destroy(su3_field f)
     if (f->owned) hipFree(f->data);
     hipFree(f->alt[0]);
     hipFree(f->alt[1]);
+    hipFree(f->alt[2]);
     hipFree(f->aux8);
     hipFree(f->d_extra);
     delete f;
@@ -1341,11 +1342,135 @@ int32_t su3_wilson_flow(su3_field f, double eps, int32_t n_steps)
     int cur = 0;
     for (int s = 0; s < n_steps; s++)
         for (int k = 0; k < 3; k++) {
-            HIPCHK(launch_flow_stage(f->prec, f->plan.grid_lw(f->d_extra + 3 + cur), eps, cz[k], ca[k], k == 0, st));
+            HIPCHK(launch_flow_stage(f->prec, f->plan.grid_lw(f->d_extra + 3 + cur), eps, cz[k], ca[k], k == 0, 0,
+                                     nullptr, st));
             cur ^= 1;
         }
     if (cur == 1) HIPCHK(hipMemcpyAsync(f->data, f->alt[0], f->bytes, hipMemcpyDeviceToDevice, st));
     return SU3_OK;
+}
+
+// E (clover energy density) and Q of the links that descriptor d points at.
+static int32_t measure_EQ(su3_field_s* f, const LatDesc* d, double* E, double* Q)
+{
+    Plan& p = f->plan;
+    HIPCHK(launch_energy_partial(f->prec, p.grid_site(d), p.d_partials, f->stream));
+    HIPCHK(launch_reduce_final(p.grid_site(d), p.d_partials, p.d_out, 1, 0, f->stream));
+    HIPCHK(launch_qtop_partial(f->prec, p.grid_site(d), p.d_partials, f->stream));
+    HIPCHK(launch_reduce_final(p.grid_site(d), p.d_partials, p.d_out, 1, 1, f->stream));
+    double r[2];
+    HIPCHK(hipMemcpyAsync(r, p.d_out, sizeof r, hipMemcpyDeviceToHost, f->stream));
+    HIPCHK(hipStreamSynchronize(f->stream));
+    *E = r[0] / f->V;
+    *Q = r[1];
+    return SU3_OK;
+}
+
+int32_t su3_wilson_flow_adaptive(su3_field f, double t_end, double tol, double max_step, double eps0,
+                                 const double* t_meas, int32_t n_meas, double* E_out, double* Q_out,
+                                 int32_t* n_accepted, int32_t* n_rejected)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!(t_end >= 0) || !std::isfinite(t_end)) return fail(SU3_ERR_ARG, "t_end must be finite and >= 0");
+    if (!(tol > 0) || !(max_step > 0) || !(eps0 > 0) || !std::isfinite(max_step))
+        return fail(SU3_ERR_ARG, "tol, max_step and eps0 must be positive");
+    if (n_meas < 0 || (n_meas > 0 && (!t_meas || !E_out || !Q_out)))
+        return fail(SU3_ERR_ARG, "measurement arrays are required for n_meas > 0");
+    for (int k = 0; k < n_meas; k++)
+        if (!std::isfinite(t_meas[k]) || t_meas[k] < 0 || t_meas[k] > t_end || (k > 0 && t_meas[k] <= t_meas[k - 1]))
+            return fail(SU3_ERR_ARG, "measurement times must ascend within [0, t_end]");
+    if ((rc = ensure_scratch(f, true, true, 3))) return rc;
+    if ((rc = single_plan(f, 2))) return rc;
+    Plan& p = f->plan;
+    hipStream_t st = f->stream;
+    // Buffers: W0 alternates between data (configuration 0) and alt0
+    // (configuration 1); alt1 holds W2, alt2 the embedded W~.
+    void* w0b[2] = { f->data, f->alt[0] };
+    void* oth[2] = { f->alt[0], f->data };
+    std::vector<LatDesc> d(6, base_desc(f));
+    for (int c = 0; c < 2; c++) {
+        LatDesc* x = &d[3 * c];
+        for (int k = 0; k < 3; k++) {
+            x[k].aux = f->aux8;
+            x[k].aux3 = f->alt[2];
+            x[k].aux4 = w0b[c];
+        }
+        x[0].U = w0b[c];
+        x[0].aux2 = oth[c];
+        x[1].U = oth[c];
+        x[1].aux2 = f->alt[1];
+        x[2].U = f->alt[1];
+        x[2].aux2 = oth[c];
+    }
+    HIPCHK(upload_descs(f->d_extra, d, st));
+    const double cz[3] = { 0.25, 8.0 / 9.0, 0.75 };
+    const double ca[3] = { 0.0, -17.0 / 9.0, -1.0 };
+    int cfg = 0, k = 0, acc = 0, rej = 0;
+    double t = 0, eps = std::min(eps0, max_step);
+    while (k < n_meas && t_meas[k] <= 0) {
+        if ((rc = measure_EQ(f, f->d_extra, &E_out[k], &Q_out[k]))) return rc;
+        k++;
+    }
+    while (t < t_end) {
+        const double target = (k < n_meas && t_meas[k] < t_end) ? t_meas[k] : t_end;
+        const bool lands = eps >= target - t;
+        const double h = lands ? target - t : eps;
+        const Grid g0 = p.grid_lw(f->d_extra + 3 * cfg);
+        for (int s = 0; s < 3; s++)
+            HIPCHK(launch_flow_stage(f->prec, p.grid_lw(f->d_extra + 3 * cfg + s), h, cz[s], ca[s], s == 0, s,
+                                     p.d_partials, st));
+        HIPCHK(launch_reduce_max(g0, p.d_partials, p.d_out, st));
+        double dist = 0;
+        HIPCHK(hipMemcpyAsync(&dist, p.d_out, sizeof dist, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (!std::isfinite(dist)) return fail(SU3_ERR_NUMERIC, "adaptive flow: non-finite error estimate");
+        if (dist <= tol) {
+            acc++;
+            cfg ^= 1;  // W3 sits in the other buffer, which now holds W0
+            t = lands ? target : t + h;
+            while (k < n_meas && t_meas[k] <= t) {
+                if ((rc = measure_EQ(f, f->d_extra + 3 * cfg, &E_out[k], &Q_out[k]))) return rc;
+                k++;
+            }
+        } else {
+            rej++;
+        }
+        eps = dist > 0 ? std::min(max_step, 0.95 * h * std::cbrt(tol / dist)) : max_step;
+        if (rej > 100000 || !(eps > 1e-12)) return fail(SU3_ERR_NUMERIC, "adaptive flow: step size collapsed");
+    }
+    if (cfg == 1) HIPCHK(hipMemcpyAsync(f->data, f->alt[0], f->bytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (n_accepted) *n_accepted = acc;
+    if (n_rejected) *n_rejected = rej;
+    return SU3_OK;
+}
+
+int32_t su3_max_plaquette_action(su3_field f, double* h)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    if (!h) return fail(SU3_ERR_ARG, "h is NULL");
+    if ((rc = single_plan(f, 1))) return rc;
+    Plan& p = f->plan;
+    HIPCHK(launch_max_splaq_partial(f->prec, p.grid_site(), p.d_partials, f->stream));
+    HIPCHK(launch_reduce_max(p.grid_site(), p.d_partials, p.d_out, f->stream));
+    HIPCHK(hipMemcpyAsync(h, p.d_out, sizeof(double), hipMemcpyDeviceToHost, f->stream));
+    HIPCHK(hipStreamSynchronize(f->stream));
+    return SU3_OK;
+}
+
+int32_t su3_flow_t0(const double* t, const double* E, int32_t n, double target, double* t0)
+{
+    if (!t || !E || !t0 || n < 2) return fail(SU3_ERR_ARG, "need t, E (n >= 2) and t0");
+    for (int k = 1; k < n; k++) {
+        const double y0 = t[k - 1] * t[k - 1] * E[k - 1], y1 = t[k] * t[k] * E[k];
+        if (y0 < target && y1 >= target) {
+            *t0 = t[k - 1] + (target - y0) * (t[k] - t[k - 1]) / (y1 - y0);
+            return SU3_OK;
+        }
+    }
+    return fail(SU3_ERR_NUMERIC, "t^2 E(t) does not cross the target between the given times");
 }
 
 int32_t su3_restrict(su3_field fine, su3_field coarse)

@@ -693,6 +693,19 @@ __device__ __forceinline__ void tiled_coords(const Geo& g, const int tile[3], in
     n[0] = 2 * x0h + ((par + n[1] + n[2] + n[3]) & 1);
 }
 
+// Largest v over a block of 256 threads; the result is valid in thread 0.
+__device__ __forceinline__ double block_max_256(double v)
+{
+    __shared__ double sh[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) v = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    return v;
+}
+
 // Logical block id with XCD-aware remapping: the hardware deals workgroups
 // round-robin over the 8 XCDs, so logical blocks are renumbered to give each
 // XCD one contiguous range of sites (neighbouring sites then share an L2).

@@ -8,6 +8,10 @@
 // (cz, ca) = (1/4, 0), (8/9, -17/9), (3/4, -1), then W <- exp(X) W.
 // X is anti-hermitian traceless, stored as (Im X00, Im X11, Re X01, Im X01,
 // Re X02, Im X02, Re X12, Im X12).
+//
+// Adaptive steps (see su3_wilson_flow_adaptive): the second stage also forms
+// the embedded second-order result exp(2 Z1 - Z0) W0 = exp(9/4 X1 + 1/4 X0) W0
+// (X0 = Z0/4, X1 = 8/9 Z1 - 17/9 X0), the third stage its distance to W3.
 #include "kernels.hpp"
 
 namespace msmc {
@@ -18,38 +22,9 @@ template <> struct FlowExpOrder<double> { static constexpr int N = 12; };
 // about 1.2e-8) is below fp32 rounding.
 template <> struct FlowExpOrder<float> { static constexpr int N = 6; };
 
-template <typename R, int NC>
-__global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double cz, double ca, int first)
+// X in 8-real form as a 3x3 anti-hermitian traceless matrix.
+template <typename R> __device__ __forceinline__ M3<R> ah_from8(const R x[8])
 {
-    const LinkWalk lw = link_walk(gr);
-    if (!lw.valid) return;
-    const LatDesc& d = gr.descs[lw.l];
-    const int mu = lw.mu, par = lw.par, cb = lw.cb, slab = 2 * mu + par;
-    const Links<R, NC> W{ (uintptr_t)d.U, d.cs };
-    const M3<R> A = staple_sum<R, NC, R>(W, d.g, mu, lw.n);
-    const M3<R> w = load_link<R, NC>(W.slab(mu, par), cb);
-    const M3<R> Om = m_mul(w, A);
-    // Z in 8-real form
-    const R tr3 = (Om.im[0] + Om.im[4] + Om.im[8]) / R(3);
-    R z[8];
-    z[0] = -Om.im[0] + tr3;
-    z[1] = -Om.im[4] + tr3;
-    z[2] = R(-0.5) * (Om.re[1] - Om.re[3]);
-    z[3] = R(-0.5) * (Om.im[1] + Om.im[3]);
-    z[4] = R(-0.5) * (Om.re[2] - Om.re[6]);
-    z[5] = R(-0.5) * (Om.im[2] + Om.im[6]);
-    z[6] = R(-0.5) * (Om.re[5] - Om.re[7]);
-    z[7] = R(-0.5) * (Om.im[5] + Om.im[7]);
-    const uintptr_t xslab = (uintptr_t)d.aux + (uintptr_t)slab * d.cs8;
-    R x[8], xo[8];
-    const R fz = (R)(cz * eps), fa = (R)ca;
-    if (!first) load_reals<R, 8>(xslab, cb, xo);
-#pragma unroll
-    for (int a = 0; a < 8; a++) {
-        x[a] = fz * z[a];
-        if (!first) x[a] += fa * xo[a];
-    }
-    store_reals<R, 8>(xslab, cb, x);
     M3<R> X;
     X.re[0] = R(0);
     X.im[0] = x[0];
@@ -69,22 +44,112 @@ __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double 
     X.im[5] = x[7];
     X.re[7] = -x[6];
     X.im[7] = x[7];
-    const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N>(X);
-    const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
-    M3<R> wn = m_mul(E, w);
-    // A 12-real record rebuilds row 2 from rows 0 and 1, so their rounding
-    // would feed back through every later product: re-orthonormalize first.
-    if constexpr (NC == 12) m_reunit(wn);
-    store_link<R, NC>(D.slab(mu, par), cb, wn);
+    return X;
 }
 
-hipError_t launch_flow_stage(int prec, const Grid& gr, double eps, double cz, double ca, int first, hipStream_t st)
+// mode 0: plain stage.  mode 1 (the second stage, X = X1 built from the
+// stored X0): also the embedded second-order result W~ = exp(2 Z1 - Z0) W0 =
+// exp(9/4 X1 + 1/4 X0) W0 into aux3, W0 read from aux4.  mode 2 (the third
+// stage): also the distance max_ij |W3 - W~| per link, block maxima into
+// partials[logical block] (0 for the padding threads).
+template <typename R, int NC>
+__global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double cz, double ca, int first, int mode,
+                                                    double* __restrict__ partials)
+{
+    const LinkWalk lw = link_walk(gr);
+    double dist = 0.0;
+    if (lw.valid) {
+        const LatDesc& d = gr.descs[lw.l];
+        const int mu = lw.mu, par = lw.par, cb = lw.cb, slab = 2 * mu + par;
+        const Links<R, NC> W{ (uintptr_t)d.U, d.cs };
+        const M3<R> A = staple_sum<R, NC, R>(W, d.g, mu, lw.n);
+        const M3<R> w = load_link<R, NC>(W.slab(mu, par), cb);
+        const M3<R> Om = m_mul(w, A);
+        // Z in 8-real form
+        const R tr3 = (Om.im[0] + Om.im[4] + Om.im[8]) / R(3);
+        R z[8];
+        z[0] = -Om.im[0] + tr3;
+        z[1] = -Om.im[4] + tr3;
+        z[2] = R(-0.5) * (Om.re[1] - Om.re[3]);
+        z[3] = R(-0.5) * (Om.im[1] + Om.im[3]);
+        z[4] = R(-0.5) * (Om.re[2] - Om.re[6]);
+        z[5] = R(-0.5) * (Om.im[2] + Om.im[6]);
+        z[6] = R(-0.5) * (Om.re[5] - Om.re[7]);
+        z[7] = R(-0.5) * (Om.im[5] + Om.im[7]);
+        const uintptr_t xslab = (uintptr_t)d.aux + (uintptr_t)slab * d.cs8;
+        R x[8], xo[8];
+        const R fz = (R)(cz * eps), fa = (R)ca;
+        if (!first) load_reals<R, 8>(xslab, cb, xo);
+#pragma unroll
+        for (int a = 0; a < 8; a++) {
+            x[a] = fz * z[a];
+            if (!first) x[a] += fa * xo[a];
+        }
+        store_reals<R, 8>(xslab, cb, x);
+        const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N>(ah_from8(x));
+        const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
+        M3<R> wn = m_mul(E, w);
+        // A 12-real record rebuilds row 2 from rows 0 and 1, so their rounding
+        // would feed back through every later product: re-orthonormalize first.
+        if constexpr (NC == 12) m_reunit(wn);
+        store_link<R, NC>(D.slab(mu, par), cb, wn);
+        if (mode == 1) {
+            R y[8];
+#pragma unroll
+            for (int a = 0; a < 8; a++) y[a] = R(2.25) * x[a] + R(0.25) * xo[a];
+            const Links<R, NC> W0{ (uintptr_t)d.aux4, d.cs };
+            M3<R> wt = m_mul(m_exp_ah<R, FlowExpOrder<R>::N>(ah_from8(y)), load_link<R, NC>(W0.slab(mu, par), cb));
+            if constexpr (NC == 12) m_reunit(wt);
+            const Links<R, NC> T{ (uintptr_t)d.aux3, d.cs };
+            store_link<R, NC>(T.slab(mu, par), cb, wt);
+        } else if (mode == 2) {
+            const Links<R, NC> T{ (uintptr_t)d.aux3, d.cs };
+            M3<R> wt = load_link<R, NC>(T.slab(mu, par), cb);
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                const double dr = (double)wn.re[k] - (double)wt.re[k], di = (double)wn.im[k] - (double)wt.im[k];
+                dist = fmax(dist, sqrt(dr * dr + di * di));
+            }
+        }
+    }
+    if (mode == 2) {
+        dist = block_max_256(dist);
+        if (threadIdx.x == 0) partials[logical_block(blockIdx.x, gr.nblocks, gr.remap)] = dist;
+    }
+}
+
+// Largest of a lattice's block partials (one block per lattice).
+__global__ void __launch_bounds__(256) k_reduce_max(const int* __restrict__ bbeg, const double* __restrict__ partials,
+                                                    double* __restrict__ out)
+{
+    const int l = blockIdx.x;
+    double v = 0.0;
+    for (int k = bbeg[l] + (int)threadIdx.x; k < bbeg[l + 1]; k += 256) v = fmax(v, partials[k]);
+    v = block_max_256(v);
+    if (threadIdx.x == 0) out[l] = v;
+}
+
+hipError_t launch_reduce_max(const Grid& gr, const double* partials, double* out, hipStream_t st)
+{
+    if (gr.nlat <= 0) return hipSuccess;
+    k_reduce_max<<<gr.nlat, 256, 0, st>>>(gr.bbeg, partials, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_stage(int prec, const Grid& gr, double eps, double cz, double ca, int first, int mode,
+                             double* partials, hipStream_t st)
 {
     if (gr.nblocks <= 0) return hipSuccess;
     switch (prec) {
-    case PREC_F64: k_flow_stage<double, 18><<<gr.nblocks, gr.block, 0, st>>>(gr, eps, cz, ca, first); break;
-    case PREC_F32: k_flow_stage<float, 18><<<gr.nblocks, gr.block, 0, st>>>(gr, eps, cz, ca, first); break;
-    case PREC_F32_R12: k_flow_stage<float, 12><<<gr.nblocks, gr.block, 0, st>>>(gr, eps, cz, ca, first); break;
+    case PREC_F64:
+        k_flow_stage<double, 18><<<gr.nblocks, gr.block, 0, st>>>(gr, eps, cz, ca, first, mode, partials);
+        break;
+    case PREC_F32:
+        k_flow_stage<float, 18><<<gr.nblocks, gr.block, 0, st>>>(gr, eps, cz, ca, first, mode, partials);
+        break;
+    case PREC_F32_R12:
+        k_flow_stage<float, 12><<<gr.nblocks, gr.block, 0, st>>>(gr, eps, cz, ca, first, mode, partials);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

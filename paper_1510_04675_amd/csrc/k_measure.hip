@@ -362,6 +362,38 @@ __global__ void __launch_bounds__(256) k_loops(Grid gr, int lm, int ln, int mode
     }
 }
 
+// Admissibility measure (Sec. IV.D): per site the largest
+// s_p = 3 [1 - (1/3) Re Tr U_p] over its six plaquettes, block maxima into
+// partials[logical block] (0 for padding threads).
+template <typename R, int NC> __global__ void __launch_bounds__(256) k_max_splaq(Grid gr, double* __restrict__ partials)
+{
+    const SiteIdx s = site_index(gr);
+    double h = 0.0;
+    if (s.valid) {
+        const LatDesc& d = gr.descs[s.l];
+        const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            int npm[4];
+            shifted(s.n, d.g, mu, 1, 0, 0, npm);
+            const M3<double> umu = ld_d(U, d.g, mu, s.n);
+#pragma unroll
+            for (int nu = mu + 1; nu < 4; nu++) {
+                int npn[4];
+                shifted(s.n, d.g, nu, 1, 0, 0, npn);
+                const M3<double> X = m_mul(umu, ld_d(U, d.g, nu, npm));
+                const M3<double> Y = m_mul(ld_d(U, d.g, nu, s.n), ld_d(U, d.g, mu, npn));
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < 9; k++) t += X.re[k] * Y.re[k] + X.im[k] * Y.im[k];
+                h = fmax(h, 3.0 - t);
+            }
+        }
+    }
+    h = block_max_256(h);
+    if (threadIdx.x == 0) partials[s.lb] = h;
+}
+
 // One block per lattice: out[l * stride + off] = sum of its partials.
 __global__ void __launch_bounds__(256) k_reduce_final(const int* __restrict__ bbeg, const double* __restrict__ partials,
                                                       double* __restrict__ out, int stride, int off)
@@ -407,6 +439,13 @@ hipError_t launch_loops_partial(int prec, const Grid& gr, int m, int n, int mode
 {
     if (gr.nblocks <= 0) return hipSuccess;
     DISPATCH_PREC_M(prec, (k_loops<R, NC><<<gr.nblocks, 256, 0, st>>>(gr, m, n, mode, partials)));
+    return hipGetLastError();
+}
+
+hipError_t launch_max_splaq_partial(int prec, const Grid& gr, double* partials, hipStream_t st)
+{
+    if (gr.nblocks <= 0) return hipSuccess;
+    DISPATCH_PREC_M(prec, (k_max_splaq<R, NC><<<gr.nblocks, 256, 0, st>>>(gr, partials)));
     return hipGetLastError();
 }
 

@@ -21,7 +21,9 @@ struct LatDesc {
     void* U;       // link field
     void* aux;     // second buffer (momenta, flow generator, ping-pong links)
     void* aux2;
-    size_t cs;     // bytes per slab of U, aux2 (link records)
+    void* aux3;    // adaptive flow: embedded second-order links W~
+    void* aux4;    // adaptive flow: links at the start of the step W0
+    size_t cs;     // bytes per slab of U, aux2, aux3, aux4 (link records)
     size_t cs8;    // bytes per slab of aux (8-real records)
     Geo g;
     double beta;
@@ -124,6 +126,8 @@ hipError_t launch_reduce_final(const Grid& gr, const double* partials, double* o
 // Wilson loop sums by class (mode 0: all; 1: chi_munu, 3 classes; 2: chi,
 // 5 classes); partials hold nclass x nblocks doubles.
 hipError_t launch_loops_partial(int prec, const Grid& gr, int m, int n, int mode, double* partials, hipStream_t st);
+// per-block maxima of s_p = 3 - Re Tr U_p (admissibility)
+hipError_t launch_max_splaq_partial(int prec, const Grid& gr, double* partials, hipStream_t st);
 hipError_t launch_qtop_partial(int prec, const Grid& gr, double* partials, hipStream_t st);
 // Clover energy density summed per block (fp64).
 hipError_t launch_energy_partial(int prec, const Grid& gr, double* partials, hipStream_t st);
@@ -138,8 +142,10 @@ hipError_t launch_kinetic_partial(int prec, const Grid& gr, double* partials, hi
 
 // --- Wilson flow (k_flow.hip) ------------------------------------------------
 // aux = 2N-storage generator (8 reals per link), aux2 = destination links.
-hipError_t launch_flow_stage(int prec, const Grid& gr, double eps, double cz, double ca, int first,
-                             hipStream_t st);
+hipError_t launch_flow_stage(int prec, const Grid& gr, double eps, double cz, double ca, int first, int mode,
+                             double* partials, hipStream_t st);
+// out[l] = max of lattice l's block partials
+hipError_t launch_reduce_max(const Grid& gr, const double* partials, double* out, hipStream_t st);
 
 // --- restriction / prolongation (k_prolong.hip), fp64 fine field ------------
 hipError_t launch_restrict(int pf, const Geo& gf, const void* Uf, size_t csf, int pc, const Geo& gc, void* Uc,

@@ -309,6 +309,37 @@ def test_wilson_flow_matches_oracle(m, orc):
     assert abs(m.su3_topological_charge(f) - orc.topological_charge(d, U)) < 1e-11
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_r12"])
+def test_adaptive_flow_matches_oracle(m, orc, prec):
+    """Adaptive-step flow (tolerance 0.01, maximum step 0.2, first step 0.2
+    so that rejections occur): FP64 takes the oracle's accepted and rejected
+    steps and matches E, Q at the measurement times and the final links;
+    R12 matches E to 1e-6 relative.  Admissibility h and the t0
+    interpolation against the oracle on the same data."""
+    d = [6, 4, 8, 6]
+    U = orc.init_hot(d, 17, 0)
+    orc.sweep_hb_or(d, U, 5.9, 17, 0, 0, 6)
+    f = field(m, d, prec)
+    m.su3_field_from_host(f, U)
+    Uh = m.su3_field_to_host(f)
+    tm = [0.0, 0.2, 0.4, 0.6, 0.9, 1.2]
+    E, Q, na, nr = m.su3_wilson_flow_adaptive(f, 1.2, 0.01, 0.2, 0.2, tm)
+    Er, Qr, nar, nrr = orc.wilson_flow_adaptive(d, Uh, 1.2, 0.01, 0.2, 0.2, tm)
+    print(f"{prec}: steps {na}+{nr} rejected (oracle {nar}+{nrr}), E {E} oracle {Er}")
+    assert nrr >= 1
+    if prec == "fp64":
+        assert (na, nr) == (nar, nrr)
+        assert np.max(np.abs(E - Er)) < 1e-12 and np.max(np.abs(Q - Qr)) < 1e-11
+        assert np.max(np.abs(m.su3_field_to_host(f) - Uh)) < 1e-11
+        assert abs(m.su3_max_plaquette_action(f) - orc.max_splaq(d, Uh)) < 1e-12
+    else:
+        assert np.max(np.abs(E - Er) / Er) < 1e-6, np.abs(E - Er) / Er
+        assert abs(m.su3_max_plaquette_action(f) - orc.max_splaq(d, m.su3_field_to_host(f))) < 1e-6
+    tt = np.linspace(0.1, 2.0, 20)
+    EE = (0.05 + 0.2 * tt) / tt**2  # t^2 E crosses 0.3 at t = 1.25
+    assert abs(m.su3_flow_t0(tt, EE, 0.3) - orc.flow_t0(tt, EE, 0.3)) < 1e-15
+
+
 def test_restrict_and_prolongate_match_oracle(m, orc):
     dc = [2, 4, 2, 2]
     df = [4, 8, 4, 4]
