@@ -1,8 +1,10 @@
-"""Physics checks against numbers the paper prints: the Wilson-flow scale
-t0/a^2 of the target ensembles (Table I), measured on ensembles generated
-by this library (heat bath + overrelaxation, FP32-R12) with the adaptive
-flow (tolerance 0.01, maximum step 0.2) measured 0.01 apart around t0 and
-the linear t0 interpolation between the nearest estimates, as for Table I."""
+"""Physics checks against numbers the paper prints, on ensembles generated
+by this library (heat bath + overrelaxation):
+- the Wilson-flow scale t0/a^2 of the target ensembles (Table I), with the
+  adaptive flow (tolerance 0.01, maximum step 0.2) measured 0.01 apart
+  around t0 and the linear t0 interpolation between the nearest estimates;
+- the HMC acceptance model of App. A: Omega^(1/2)/t0 and the step count for
+  70 % acceptance (Table "tuning")."""
 import math
 import os
 
@@ -65,3 +67,52 @@ def test_t0_of_target_ensembles(m, row, n_cfg, therm, gap):
     print(f"\n{dims} beta {beta}: t0/a^2 = {mean:.5f}({sem:.5f}) from {n_cfg} configurations; "
           f"paper {t0_paper}({err_paper}); {abs(mean - t0_paper) / comb:.2f} sigma")
     assert abs(mean - t0_paper) < 4 * comb
+
+
+def golden_hmc():
+    rows = []
+    with open(os.path.join(HERE, "golden", "hmc_tuning.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = line.split()
+            rows.append(([int(x) for x in v[:4]], float(v[4]), float(v[5]), float(v[6]), float(v[7]), float(v[8])))
+    return rows
+
+
+@pytest.mark.timeout(600)
+def test_hmc_acceptance_model_12_3x24(m):
+    """12^3 x 24 at beta 5.626: 96 heat-bath configurations (one every 10
+    sweeps after 200), one unit HMC trajectory from each (FP32 molecular
+    dynamics, FP64 Hamiltonian) for 1/dtau in {24, 30, 37, 48, 64}; the
+    acceptance probability <min(1, exp(-dH))> fitted to
+    erfc(Omega^(1/2) dtau^2 / 2).  Omega^(1/2)/t0 and 1/dtau at 70 %
+    within 4 combined standard errors of the paper's."""
+    from paper_1510_04675_amd import analysis as an
+    dims, beta, om_t0, om_err, inv70, inv70_err = golden_hmc()[0]
+    t0 = golden_t0()[0][2]
+    f = m.Field(dims, "fp32")
+    g = m.Field(dims, "fp32")
+    m.su3_init_cold(f)
+    p = m.hb_params(n_or=4, reunit_every=10)
+    m.su3_sweep_hb_or(f, beta, 41, 0, 0, 200, p, record=False)
+    steps = [24, 30, 37, 48, 64]
+    pacc = {k: [] for k in steps}
+    n_cfg = 96
+    for c in range(n_cfg):
+        m.su3_sweep_hb_or(f, beta, 41, 0, 200 + 10 * c, 10, p, record=False)
+        for k in steps:
+            m.su3_field_copy(g, f)
+            _, dh = m.su3_hmc_trajectory(g, beta, 1.0, k, 41, 0, 1000 * c + k, 0)
+            pacc[k].append(min(1.0, math.exp(-dh)))
+    dtau = 1.0 / np.array(steps, float)
+    acc = np.array([np.mean(pacc[k]) for k in steps])
+    sem = np.array([np.std(pacc[k], ddof=1) / math.sqrt(n_cfg) for k in steps])
+    n_eff = np.clip(acc * (1 - acc) / np.maximum(sem, 1e-6) ** 2, 1, None)
+    om, om_fit_err, inv = an.fit_acceptance(dtau, acc, n_eff)
+    om_ref = om_t0 * t0
+    print(f"\nacceptance {np.round(acc, 3).tolist()} at 1/dtau {steps}; Omega^1/2 = {om:.1f}({om_fit_err:.1f}) "
+          f"= {om / t0:.0f} t0 (paper {om_t0:.0f}({om_err:.0f}) t0); 1/dtau(70%) = {inv:.1f} (paper {inv70}({inv70_err}))")
+    assert abs(om - om_ref) < 4 * math.hypot(om_fit_err, om_err * t0)
+    inv_err = inv * 0.5 * om_fit_err / om  # 1/dtau_70 scales as sqrt(Omega^1/2)
+    assert abs(inv - inv70) < 4 * math.hypot(inv_err, inv70_err)
