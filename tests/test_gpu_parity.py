@@ -404,3 +404,70 @@ def test_full_size_32_4_fp32_sweep_tracks_oracle(m, orc):
     assert abs(h[0] - href[0]) < 1e-6
     assert med < 1e-5 and q999 < 1e-3
     assert np.count_nonzero(dev > 1e-2) <= dev.size // 10000
+
+
+def test_smallest_extents_match_oracle(m, orc):
+    """Extent 2 in every direction (n + mu = n - mu) and mixed 2/4/6 extents:
+    FP64 sweeps per link against the oracle."""
+    for d in ([2, 2, 2, 2], [2, 4, 2, 6]):
+        f = field(m, d)
+        m.su3_init_hot(f, 23, 0)
+        h = m.su3_sweep_hb_or(f, 6.0, 23, 0, 0, 3, P(n_or=2))
+        U = orc.init_hot(d, 23, 0)
+        href, _ = orc.sweep_hb_or(d, U, 6.0, 23, 0, 0, 3, n_or=2)
+        assert np.max(np.abs(h - href)) < 1e-13, d
+        assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12, d
+
+
+def test_errors_and_empty_work(m, orc):
+    """Validation failures return status codes and leave fields untouched;
+    zero sweeps and zero steps are no-ops."""
+    import paper_1510_04675_amd as msmc
+    for bad in ([3, 4, 4, 4], [4, 4, 0, 4], [1, 2, 2, 2]):
+        with pytest.raises(msmc.SU3Error) as e:
+            m.Field(bad, "fp64")
+        assert e.value.code == 2
+    f = field(m, [4, 4, 4, 4])
+    m.su3_init_hot(f, 3, 0)
+    before = m.su3_field_to_host(f)
+    with pytest.raises(msmc.SU3Error) as e:
+        m.su3_sweep_hb_or(f, 6.0, 3, 0, 0, 1, P(n_or=-1))
+    assert e.value.code == 1
+    with pytest.raises(msmc.SU3Error) as e:
+        m.su3_sweep_hb_or(f, float("nan"), 3, 0, 0, 1, P())
+    assert e.value.code == 1
+    coarse = field(m, [2, 2, 2, 4])
+    with pytest.raises(msmc.SU3Error) as e:
+        m.su3_prolongate(coarse, f)
+    assert e.value.code == 2
+    with pytest.raises(msmc.SU3Error) as e:
+        m.su3_batch_sweep_hb_or([f, f], [6.0, 6.0], [1, 1], [0, 1], 0, 1, P())
+    assert e.value.code == 1
+    g = field(m, [4, 4, 4, 4], "fp32")
+    with pytest.raises(msmc.SU3Error) as e:
+        m.su3_batch_sweep_hb_or([f, g], [6.0, 6.0], [1, 1], [0, 1], 0, 1, P())
+    assert e.value.code == 6
+    with pytest.raises(msmc.SU3Error) as e:
+        m.su3_wilson_loop(f, 0, 1)
+    assert e.value.code == 1
+    with pytest.raises(msmc.SU3Error) as e:
+        m.su3_wilson_flow_adaptive(f, 1.0, 0.01, 0.2, 0.01, [0.5, 0.2])
+    assert e.value.code == 1
+    assert np.array_equal(m.su3_field_to_host(f), before)
+    m.su3_sweep_hb_or(f, 6.0, 3, 0, 0, 0, P())
+    m.su3_wilson_flow(f, 0.01, 0)
+    m.su3_batch_sweep_hb_or([f], [6.0], [3], [0], 0, 0, P())
+    assert np.array_equal(m.su3_field_to_host(f), before)
+
+
+def test_large_lattice_48_4_fp64_sweep_matches_oracle(m, orc):
+    """48^4 (5.3 M sites, 3 GB of FP64 links; slabs of 382 MB): one sweep of
+    1 HB + 1 OR per link against the oracle, in the benchmark's launch path."""
+    d = [48, 48, 48, 48]
+    f = field(m, d)
+    m.su3_init_hot(f, 29, 0)
+    h = m.su3_sweep_hb_or(f, 6.0, 29, 0, 0, 1, P(n_or=1))
+    U = orc.init_hot(d, 29, 0)
+    href, _ = orc.sweep_hb_or(d, U, 6.0, 29, 0, 0, 1, n_or=1)
+    assert abs(h[0] - href[0]) < 1e-13
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
