@@ -182,6 +182,40 @@ def run_multiscale(m, torch, L=32, beta_c=5.7, beta=6.0, n_coarse=20, n_sweeps=2
     return out
 
 
+def run_batch48(m, torch, prec="fp32", n_sweeps=100):
+    """48 prolongated lattices of uneven sizes (16 each of 12^4, 16^4, 20^4),
+    beta_i uniform in [5.9, 6.2] (numpy PCG64 seed 4), coarse (L/2)^4 hot
+    starts (seed 4, lattice id i) with 20 sweeps at beta_i - 0.36, then
+    n_sweeps HB+OR sweeps of all 48 in one batched graph launch."""
+    import synth_inputs as si
+    sizes = [12] * 16 + [16] * 16 + [20] * 16
+    betas = si.batch_betas(48, 4)
+    fields = []
+    for i, L in enumerate(sizes):
+        c = m.Field([L // 2] * 4, "fp64")
+        m.su3_init_hot(c, 4, i)
+        m.su3_sweep_hb_or(c, betas[i] - 0.36, 4, i, 0, 20, m.hb_params(n_or=4), record=False)
+        f = m.Field([L] * 4, prec)
+        m.su3_prolongate(c, f, 0.05, 1e-5, 10000)
+        c.close()
+        fields.append(f)
+    p = m.hb_params(n_or=4, reunit_every=10)
+    m.su3_batch_sweep_hb_or(fields, betas, [4] * 48, list(range(48)), 0, n_sweeps, p)  # builds the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = m.su3_batch_sweep_hb_or(fields, betas, [4] * 48, list(range(48)), n_sweeps, n_sweeps, p)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    links = sum(4 * L**4 for L in sizes)
+    out = {"lattices": "16 x 12^4 + 16 x 16^4 + 16 x 20^4", "links": links, "storage": prec, "sweeps": n_sweeps,
+           "seconds": round(dt, 4), "link_updates_per_s": round(5 * links * n_sweeps / dt, 1),
+           "plaquette_last_sweep_by_beta": [[round(float(b), 4), round(float(x), 6)]
+                                            for b, x in sorted(zip(betas, h[-1]))][::8]}
+    for f in fields:
+        f.close()
+    return out
+
+
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
@@ -258,11 +292,12 @@ def main():
     ap.add_argument("--lattice", type=int, default=32)
     ap.add_argument("--batch", type=int, default=4, help="lattices in the FP32 batched run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of parts to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch,hmc,multiscale)")
+    ap.add_argument("--only", default="", help="comma list of parts to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch,hmc,multiscale,batch48)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-hmc", action="store_true", help="skip the HMC report")
     ap.add_argument("--no-multiscale", action="store_true", help="skip the prolongation / displaced-loop report")
+    ap.add_argument("--no-batch48", action="store_true", help="skip the 48-lattice batched run")
     ap.add_argument("--launch", default="", help="fix the launch shape block,xcd_remap,ty,tz,tt (implies --no-tune)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -308,8 +343,13 @@ def main():
         log("bench: multiscale (16^4 -> 32^4 prolongation, displaced loops) ...")
         ms = run_multiscale(m, torch, L)
         log(f"bench: prolongation {ms['prolongation_ms']} ms, displaced spread {ms['displaced_spread_vs_sweeps']}")
-    if head is None:  # only the HMC / multiscale parts were asked for
-        print(json.dumps({"hmc": hmc, "multiscale": ms}), flush=True)
+    b48 = None
+    if not a.no_batch48 and (not a.only or "batch48" in want):
+        log("bench: 48 prolongated lattices (12^4, 16^4, 20^4), 100 sweeps in one graph ...")
+        b48 = {prec: run_batch48(m, torch, prec) for prec in ("fp32", "fp32_r12")}
+        log("bench: batch48 " + ", ".join(f"{k} {v['link_updates_per_s']:.3e} link updates/s" for k, v in b48.items()))
+    if head is None:  # only the HMC / multiscale / batch48 parts were asked for
+        print(json.dumps({"hmc": hmc, "multiscale": ms, "batch48": b48}), flush=True)
         return
     cpu = None
     if not a.no_cpu_baseline:
@@ -349,6 +389,8 @@ def main():
         line["hmc"] = hmc
     if ms is not None:
         line["multiscale"] = ms
+    if b48 is not None:
+        line["batch48"] = b48
     if "fp64" in res:
         # every variant's lattice 0 starts from the same hot start and draws the
         # same uniforms, so its first sweep is comparable with the fp64 one
