@@ -76,8 +76,10 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
     }
     return c;
@@ -185,9 +187,15 @@ __device__ __forceinline__ double fs_exp(double y)
 
 // math wrappers per precision
 __device__ __forceinline__ double m_log(double x) { return fs_ln(x); }
-__device__ __forceinline__ float m_log(float x) { return logf(x); }
+// fp32 draws: the hardware logarithm (the arguments are normal numbers in
+// (0, 1]); fp32 is never compared with fp64 bit for bit.
+__device__ __forceinline__ float m_log(float x) { return __logf(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+// 1 / sqrt(x): the fp64 form is the exact IEEE sequence, fp32 the hardware
+// reciprocal square root
+__device__ __forceinline__ double m_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float m_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double m_exp(double x) { return fs_exp(x); }
 __device__ __forceinline__ float m_exp(float x) { return expf(x); }
 // (cos 2 pi u, sin 2 pi u)
@@ -345,7 +353,7 @@ template <typename R> __device__ __forceinline__ void m_reunit(M3<R>& a)
     R n0 = R(0);
 #pragma unroll
     for (int c = 0; c < 3; c++) n0 += a.re[c] * a.re[c] + a.im[c] * a.im[c];
-    n0 = R(1) / m_sqrt(n0);
+    n0 = m_rsqrt(n0);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         a.re[c] *= n0;
@@ -365,7 +373,7 @@ template <typename R> __device__ __forceinline__ void m_reunit(M3<R>& a)
     R n1 = R(0);
 #pragma unroll
     for (int c = 0; c < 3; c++) n1 += a.re[3 + c] * a.re[3 + c] + a.im[3 + c] * a.im[3 + c];
-    n1 = R(1) / m_sqrt(n1);
+    n1 = m_rsqrt(n1);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         a.re[3 + c] *= n1;
@@ -394,8 +402,9 @@ template <typename R> __device__ __forceinline__ R su2_part(const M3<R>& W, int 
     R x3 = (W.im[ii] - W.im[jj]) * R(0.5);
     R x1 = (W.im[ij] + W.im[ji]) * R(0.5);
     R x2 = (W.re[ij] - W.re[ji]) * R(0.5);
-    R k = m_sqrt(x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
-    R ik = (k > R(0)) ? R(1) / k : R(0);
+    const R k2 = x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3;
+    const R ik = (k2 > R(0)) ? m_rsqrt(k2) : R(0);
+    const R k = k2 * ik;
     v.q0 = x0 * ik;
     v.q1 = x1 * ik;
     v.q2 = x2 * ik;

@@ -41,20 +41,31 @@ __device__ __forceinline__ int find_lattice_p(const int* __restrict__ bbeg, int 
 template <typename R>
 __device__ __forceinline__ bool draw_g0(const Rng& rng, R alpha, int mu, int sg, int h, const HbArgs& hb, R& g0)
 {
+    // fp64 divides by alpha exactly as the reference order does; fp32 scales
+    // by the reciprocal
+    const R ia = R(1) / alpha;
     for (int t = 0; t < hb.max_tries; t++) {
         const uint4 w = rng.draw(ctr_word(P_HB, mu, sg, h, t));
         const R u0 = u01<R>(w.x), u1 = u01<R>(w.y), u2 = u01<R>(w.z), u3 = u01<R>(w.w);
         if (hb.sampler == 0) {
             R cs, sn;
             m_cossin2pi(u1, &cs, &sn);
-            const R delta = -(m_log(u0) + cs * cs * m_log(u2)) / alpha;
+            R delta;
+            if constexpr (std::is_same<R, double>::value)
+                delta = -(m_log(u0) + cs * cs * m_log(u2)) / alpha;
+            else
+                delta = -(m_log(u0) + cs * cs * m_log(u2)) * ia;
             if (u3 * u3 <= R(1) - R(0.5) * delta) {
                 g0 = R(1) - delta;
                 return true;
             }
         } else {
             const R e = m_exp(R(-2) * alpha);
-            const R x = R(1) + m_log(e + u0 * (R(1) - e)) / alpha;
+            R x;
+            if constexpr (std::is_same<R, double>::value)
+                x = R(1) + m_log(e + u0 * (R(1) - e)) / alpha;
+            else
+                x = R(1) + m_log(e + u0 * (R(1) - e)) * ia;
             if (u1 * u1 <= R(1) - x * x) {
                 g0 = x;
                 return true;
