@@ -11,7 +11,9 @@ workload.  One link update = one link through one pass, so a 32^4 sweep is
 Printed: one JSON line (rank 0) with the headline value (FP32-R12 batched
 link updates/s), the FP64 single-lattice figure, the roofline of the
 dominant kernel (the overrelaxation phase) from HIP events recorded around
-every phase launch, and the FP64 CPU oracle timed on a bounded sample.
+each run of same-kind phase launches, and the FP64 CPU oracle timed on a
+bounded sample.  Extra reports: HMC at 32^4, a multiscale step (16^4 -> 32^4
+prolongation, rethermalization, flow) and the 48-lattice batch.
 """
 from __future__ import annotations
 
@@ -43,7 +45,7 @@ def log(msg):
 
 def run_variant(m, torch, prec, n_lat, dims, steps, warmup, beta=6.0, n_or=4):
     """Time `steps` sweeps of n_lat lattices (batched graph path), then
-    `steps` more with per-phase HIP events to get kernel durations."""
+    `steps` more launched eagerly with HIP events to get kernel durations."""
     fields = [m.Field(dims, prec) for _ in range(n_lat)]
     for i, f in enumerate(fields):
         m.su3_init_hot(f, 3, i)
@@ -71,7 +73,8 @@ def run_variant(m, torch, prec, n_lat, dims, steps, warmup, beta=6.0, n_or=4):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
-    # kernel durations: same kernels launched eagerly with events around each phase
+    # kernel durations: same kernels launched eagerly with events around each
+    # run of same-kind phases (heat bath, overrelaxation, plaquette)
     m.su3_profile_enable(True)
     for _ in range(steps):
         m.su3_batch_sweep_hb_or(fields, betas, seeds, lids, sweep, 1, params)
@@ -171,8 +174,23 @@ def run_multiscale(m, torch, L=32, beta_c=5.7, beta=6.0, n_coarse=20, n_sweeps=2
         t_sw += time.perf_counter() - t0
         d = m.su3_displaced_loops(f)
         curve.append([k + every, float(d.max() - d.min())])
+    # measurement after flow of the rethermalized field, R12 against FP64 from
+    # the same links: adaptive flow (tolerance 0.01, maximum step 0.2) to t = 1
+    g = m.Field([L] * 4, "fp64")
+    m.su3_field_copy(g, f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E12, Q12, na, nr = m.su3_wilson_flow_adaptive(f, 1.0, 0.01, 0.2, 0.01, [0.5, 1.0])
+    torch.cuda.synchronize()
+    t_flow = time.perf_counter() - t0
+    E64, Q64, _, _ = m.su3_wilson_flow_adaptive(g, 1.0, 0.01, 0.2, 0.01, [0.5, 1.0])
+    p12, p64 = m.su3_plaquette(f), m.su3_plaquette(g)
+    g.close()
     out = {"coarse": f"{L // 2}^4 hot start (seed 11), {n_coarse} sweeps at beta {beta_c}",
            "fine": f"{L}^4, R12 rethermalization at beta {beta}",
+           "flow_to_t1_ms_r12": round(1e3 * t_flow, 2), "flow_steps": [na, nr],
+           "after_flow_r12_vs_fp64": {"plaquette": [p12, p64, abs(p12 - p64)], "E": [float(E12[-1]), float(E64[-1])],
+                                      "Q": [float(Q12[-1]), float(Q64[-1]), abs(float(Q12[-1] - Q64[-1]))]},
            "prolongation_ms": round(1e3 * t_pro, 2), "ape_steps_per_stage": [int(x) for x in iters],
            "displaced_loops_ms": round(1e3 * t_loops, 3),
            "displaced_2x2_after_prolongation": [round(float(x), 6) for x in dl],
