@@ -254,12 +254,15 @@ def recorded_traffic(v, lattice):
     launch shape; otherwise None."""
     try:
         with open(os.path.join(ROOT, TRAFFIC_SUMMARY)) as fh:
-            rec = next(json.loads(line.split(":", 1)[1]) for line in fh if line.startswith("traffic-record:"))
-    except (OSError, StopIteration, ValueError):
+            recs = [json.loads(line.split(":", 1)[1]) for line in fh if line.startswith("traffic-record:")]
+    except (OSError, ValueError):
         return None
-    same = (rec.get("sources_sha256") == kernel_sources_hash() and rec.get("launch") == launch_str(v["launch"])
-            and rec.get("prec") == v["prec"] and rec.get("n_lat") == v["n_lat"] and rec.get("lattice") == lattice)
-    return rec.get("hbm_bytes_per_launch") if same else None
+    sha = kernel_sources_hash()
+    for rec in recs:
+        if (rec.get("sources_sha256") == sha and rec.get("launch") == launch_str(v["launch"])
+                and rec.get("prec") == v["prec"] and rec.get("n_lat") == v["n_lat"] and rec.get("lattice") == lattice):
+            return rec.get("hbm_bytes_per_launch")
+    return None
 
 
 def roofline(v, lattice=32):
