@@ -471,3 +471,37 @@ def test_large_lattice_48_4_fp64_sweep_matches_oracle(m, orc):
     href, _ = orc.sweep_hb_or(d, U, 6.0, 29, 0, 0, 1, n_or=1)
     assert abs(h[0] - href[0]) < 1e-13
     assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
+
+
+def test_library_owned_field_and_stream(m, orc):
+    """A field the library allocates itself (su3_field_create) on a separate
+    HIP stream gives bitwise the result of a torch-wrapped field; info reports
+    shape, precision and size; destroy frees it."""
+    import ctypes as C
+
+    import torch
+
+    import paper_1510_04675_amd as msmc
+    lib = msmc.lib()
+    d = [4, 6, 4, 2]
+    s = torch.cuda.Stream()
+    dims = (C.c_int32 * 4)(*d)
+    h = C.c_void_p()
+    assert lib.su3_field_create(dims, 2, C.c_void_p(s.cuda_stream), C.byref(h)) == 0
+
+    class Raw:
+        handle = h
+        volume = int(np.prod(d))
+
+    out_dims = (C.c_int32 * 4)()
+    prec, nbytes = C.c_int32(), C.c_size_t()
+    assert lib.su3_field_info(h, out_dims, C.byref(prec), C.byref(nbytes)) == 0
+    assert list(out_dims) == d and prec.value == 2 and nbytes.value == m.su3_field_bytes(d, 2)
+    m.su3_init_hot(Raw, 8, 1)
+    hr = m.su3_sweep_hb_or(Raw, 6.0, 8, 1, 0, 2, P(n_or=2, reunit=1))
+    f = field(m, d, "fp32_r12")
+    m.su3_init_hot(f, 8, 1)
+    hf = m.su3_sweep_hb_or(f, 6.0, 8, 1, 0, 2, P(n_or=2, reunit=1))
+    assert np.array_equal(hr, hf)
+    assert np.array_equal(m.su3_field_to_host(Raw), m.su3_field_to_host(f))
+    assert lib.su3_field_destroy(h) == 0
