@@ -165,6 +165,9 @@ def run_multiscale(m, torch, L=32, beta_c=5.7, beta=6.0, n_coarse=20, n_sweeps=2
     f64.close()
     c.close()
     curve = [[0, float(dl.max() - dl.min())]]
+    # a call without sweeps runs the launch-shape autotuner (when enabled)
+    # for this field shape, outside the timed rethermalization
+    m.su3_sweep_hb_or(f, beta, 11, 0, 1000, 0, m.hb_params(n_or=4, reunit_every=10), record=False)
     t_sw = 0.0
     for k in range(0, n_sweeps, every):
         torch.cuda.synchronize()

@@ -238,8 +238,8 @@ int32_t su3_last_exhausted(su3_field f, int64_t* count);
  * 512}, xcd_remap in {0, 1}; block = 0 restores automatic choice.
  * Results do not depend on it.  su3_autotune(1) makes the next sweep call
  * time the candidates (3 blocks x 2 remaps x 7 tiles) on cold-start scratch
- * fields of the same shapes with 1 HB + 4 OR sweeps and keep the fastest for
- * those shapes; the default (256, remap, tile 16 x 8 x 4) is kept unless
+ * fields of the same shapes, swept at that call's couplings and options, and
+ * keep the fastest for those shapes; the default (256, remap, tile 16 x 8 x 4) is kept unless
  * another shape is faster by more than 1.5 %.  The scratch fields are
  * allocated and freed inside that call. */
 int32_t su3_set_launch(int32_t block, int32_t xcd_remap);

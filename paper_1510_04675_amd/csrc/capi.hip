@@ -541,10 +541,13 @@ static int32_t validate_hb(const su3_hb_params* pp, SweepOpts& o)
 }
 
 // Time each launch shape on scratch fields (cold starts) of the given shapes
-// with sweeps of 1 HB + 4 OR passes, and remember the fastest for this shape
-// set; the default shape is kept unless another is faster by more than 1.5 %
-// (differences below that are run-to-run noise).
-static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
+// with sweeps of the calling sweep's own couplings and options, and remember
+// the fastest for this shape set; the default shape is kept unless another is
+// faster by more than 1.5 % (differences below that are run-to-run noise).
+// The couplings matter: at beta = 0 every heat-bath trial is rejected, so a
+// pass costs several times what it does at the couplings of interest.
+static int32_t autotune(const std::vector<su3_field_s*>& fs, const double* betas, const SweepOpts& call,
+                        hipStream_t st)
 {
     std::vector<su3_field_s> scratch(fs.size());
     std::vector<su3_field_s*> sp;
@@ -587,16 +590,18 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, hipStream_t st)
         {
             rc = plan_build(p, sp, cand[ci], 1, st);
             if (rc) break;
-            if (ci == 0) {
-                for (size_t i = 0; i < sp.size(); i++) p.host_descs[i].seed = 12345u + (uint32_t)i;
-                if (upload_descs(p.d_descs, p.host_descs, st) != hipSuccess ||
-                    launch_init(p.prec, 0, p.grid_link(), st) != hipSuccess) {
-                    rc = fail(SU3_ERR_HIP, "autotune init failed");
-                    break;
-                }
+            for (size_t i = 0; i < sp.size(); i++) {
+                p.host_descs[i].seed = 12345u + (uint32_t)i;
+                p.host_descs[i].beta = betas[i];
+            }
+            if (upload_descs(p.d_descs, p.host_descs, st) != hipSuccess ||
+                (ci == 0 && launch_init(p.prec, 0, p.grid_link(), st) != hipSuccess)) {
+                rc = fail(SU3_ERR_HIP, "autotune init failed");
+                break;
             }
             k_set_u64<<<1, 1, 0, st>>>(p.d_sweep, 0);
-            SweepOpts o{ 4, 1, 64, 0, 0, false };
+            SweepOpts o = call;
+            o.record = false;
             rc = enqueue_sweeps(p, 1, o, st, nullptr);  // warm-up
             if (rc) break;
             hipEventRecord(e0, st);
@@ -918,7 +923,7 @@ int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattic
             std::lock_guard<std::mutex> lk(g_mu);
             have = g_tuned.count(shape_key(fs)) > 0;
         }
-        if (!have && (rc = autotune(fs, f->stream))) return rc;
+        if (!have && (rc = autotune(fs, &beta, o, f->stream))) return rc;
     }
     if ((rc = single_plan(f, std::max(1, n_sweeps)))) return rc;
     Plan& p = f->plan;
@@ -976,7 +981,7 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
             std::lock_guard<std::mutex> lk(g_mu);
             have = g_tuned.count(shape_key(v)) > 0;
         }
-        if (!have && (rc = autotune(v, st))) return rc;
+        if (!have && (rc = autotune(v, betas, o, st))) return rc;
     }
     const LaunchCfg cfg = launch_choice(v);
     std::string key = std::to_string(n_sweeps) + "|" + std::to_string(o.n_or) + "," + std::to_string(o.n_hits) +
@@ -1503,49 +1508,45 @@ int32_t su3_prolongate(su3_field coarse, su3_field fine, double c, double rel_to
     const size_t csf = slab_bytes(fine->Vh, 18, 8);
     const size_t nbytes = 8 * csf;
     double* buf[2] = { nullptr, nullptr };
-    const int nb = ceil_div(2LL * fine->Vh, 256);
+    const int nb = std::max({ ape_blocks(gf, 0), ape_blocks(gf, 1), ape_blocks(gf, 2) });
     double* bs = nullptr;
+    void* state = nullptr;
     if (hipMalloc(&buf[0], nbytes) != hipSuccess || hipMalloc(&buf[1], nbytes) != hipSuccess ||
-        hipMalloc(&bs, sizeof(double) * nb) != hipSuccess) {
+        hipMalloc(&bs, sizeof(double) * nb) != hipSuccess || hipMalloc(&state, ape_state_bytes()) != hipSuccess) {
         hipFree(buf[0]);
         hipFree(buf[1]);
         hipFree(bs);
+        hipFree(state);
         return fail(SU3_ERR_NOMEM, "prolongation scratch allocation failed");
     }
-    std::vector<double> hb(nb);
-    auto partial = [&](const double* U, int d, double* out) -> hipError_t {
-        hipError_t e = launch_partial_action(gf, U, csf, d, bs, nb, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(hb.data(), bs, sizeof(double) * nb, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        double s = 0;
-        for (int b = 0; b < nb; b++) s += hb[b];
-        *out = s;
-        return e;
-    };
     hipError_t e = launch_transfer(coarse->prec, coarse->geo(), coarse->data, coarse->cs, gf, buf[0], csf, st);
     int cur = 0;
     int iters[3] = { 0, 0, 0 };
+    // Steps are enqueued in runs of `run` without waiting; the stage's state
+    // on the device turns the steps after the stopping point into no-ops.
+    const int run = 16;
     for (int d = 0; d < 3 && e == hipSuccess; d++) {
-        double s_prev = 0;
-        e = partial(buf[cur], d, &s_prev);
-        int k = 0;
-        while (e == hipSuccess && k < max_iter) {
-            e = launch_ape(gf, buf[cur], buf[cur ^ 1], csf, d, c, st);
-            cur ^= 1;
-            k++;
-            double s = 0;
-            if (e == hipSuccess) e = partial(buf[cur], d, &s);
-            const bool done = std::fabs(s - s_prev) <= rel_tol * s_prev;
-            s_prev = s;
-            if (done) break;
+        // a step writes only the bonds of stage d: both buffers start the
+        // stage with the same links
+        e = hipMemcpyAsync(buf[cur ^ 1], buf[cur], nbytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = launch_ape_reset(state, st);
+        const int nbd = ape_blocks(gf, d);
+        int done = max_iter == 0, k = 0;
+        for (int j = 1; e == hipSuccess && !done; j++) {
+            // step j reads iterate j-1 from buf[cur ^ ((j-1) & 1)]
+            const int src = cur ^ ((j - 1) & 1);
+            e = launch_ape_step(gf, buf[src], buf[src ^ 1], csf, d, c, j, rel_tol, max_iter, state, bs, nbd, st);
+            if (e == hipSuccess && (j % run == 0 || j >= max_iter)) e = read_ape_state(state, &done, &k, st);
         }
         iters[d] = k;
+        cur ^= k & 1;
     }
     if (e == hipSuccess) e = launch_convert(fine->prec, fine->data, fine->cs, PREC_F64, buf[cur], csf, fine->Vh, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     hipFree(buf[0]);
     hipFree(buf[1]);
     hipFree(bs);
+    hipFree(state);
     if (e != hipSuccess) return fail(SU3_ERR_HIP, std::string("prolongate: ") + hipGetErrorString(e));
     if (iters_out)
         for (int d = 0; d < 3; d++) iters_out[d] = iters[d];

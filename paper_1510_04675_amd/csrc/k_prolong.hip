@@ -116,41 +116,33 @@ __device__ M3<double> project_su3(const M3<double>& M)
     return X;
 }
 
-__global__ void __launch_bounds__(256) k_ape(Geo g, const double* __restrict__ Uold, double* __restrict__ Unew,
-                                             size_t cs, int d, double c)
+// The bonds a stage updates, grouped in classes: a direction mu and the set
+// of other coordinates that are odd (a bit mask, bit m for coordinate m).
+// Each class holds V/8 sites: n_mu takes every value, each other coordinate
+// the values of its parity.  Thread t maps to class t / (V/8) and to a site
+// of that class, coordinate 0 fastest, so that a wavefront reads consecutive
+// checkerboard sites.
+struct BondClasses {
+    int n;
+    int mu[12];
+    int odd[12];
+};
+
+// Site r of a class: coordinates in the mask `free` take every value, the
+// others the values of the parity given by `odd`; coordinate 0 fastest.
+__device__ __forceinline__ void class_site(const Geo& g, int free, int odd, int r, int n[4])
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 8 * g.Vh) return;
-    int mu, par, cb, n[4];
-    link_of(g, e, mu, par, cb, n);
-    const Links<double, 18> U{ (uintptr_t)Uold, cs };
-    const M3<double> u = load_link<double, 18>(U.slab(mu, par), cb);
-    const uintptr_t dst = (uintptr_t)Unew + (uintptr_t)(mu * 2 + par) * cs;
-    if (n_odd_excl(n, mu, mu) != d + 1) {
-        store_link<double, 18>(dst, cb, u);
-        return;
-    }
-    // M = U + c (T+ + T-) added direction by direction, nu ascending
-    M3<double> M = u;
-    for (int nu = 0; nu < 4; nu++) {
-        if (nu == mu || n_odd_excl(n, mu, nu) != d) continue;
-        int npn[4] = { n[0], n[1], n[2], n[3] }, npm[4] = { n[0], n[1], n[2], n[3] }, nmn[4] = { n[0], n[1], n[2], n[3] };
-        npn[nu] = wrap_add(n[nu], 1, g.L[nu]);
-        npm[mu] = wrap_add(n[mu], 1, g.L[mu]);
-        nmn[nu] = wrap_add(n[nu], -1, g.L[nu]);
-        int nmn_pm[4] = { nmn[0], nmn[1], nmn[2], nmn[3] };
-        nmn_pm[mu] = npm[mu];
-        // T+ = U_nu(n) U_mu(n+nu) U_nu(n+mu)^+
-        M3<double> T = m_mul_nd(m_mul(load_at(U, g, nu, n), load_at(U, g, mu, npn)), load_at(U, g, nu, npm));
-        // T- = U_nu(n-nu)^+ U_mu(n-nu) U_nu(n-nu+mu)
-        m_acc(T, m_mul(m_mul_dn(load_at(U, g, nu, nmn), load_at(U, g, mu, nmn)), load_at(U, g, nu, nmn_pm)));
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
-            M.re[k] += T.re[k] * c;
-            M.im[k] += T.im[k] * c;
+    for (int m = 0; m < 4; m++) {
+        if ((free >> m) & 1) {
+            n[m] = r % g.L[m];
+            r /= g.L[m];
+        } else {
+            const int h = g.L[m] >> 1;
+            n[m] = 2 * (r % h) + ((odd >> m) & 1);
+            r /= h;
         }
     }
-    store_link<double, 18>(dst, cb, project_su3(M));
 }
 
 __device__ __forceinline__ double block_sum_256p(double v)
@@ -165,30 +157,96 @@ __device__ __forceinline__ double block_sum_256p(double v)
     return v;
 }
 
-// sum over plaquettes with chi_munu(n) = d of 1 - (1/3) Re Tr U_munu(n)
-__global__ void __launch_bounds__(256) k_partial_action(Geo g, const double* __restrict__ Ud, size_t cs, int d,
-                                                        double* __restrict__ bsum)
+// Progress of one interpolation stage, kept on the device so that steps can
+// be enqueued without a host round trip per step: s_prev is the partial
+// action of the last iterate seen, done is set (with iters, the number of
+// steps of the result) once the stopping rule holds or max_iter is reached.
+struct ApeState {
+    double s_prev;
+    int done;
+    int iters;
+};
+
+// Step j of stage d (reads iterate j-1, writes iterate j) on the bonds with
+// chi_mu(n) = d + 1 only; Unew must already hold every other bond (they do
+// not change in a stage).  It also returns, as block sums, the partial action
+// S_d of iterate j-1: each plaquette of S_d contains exactly two updated bonds
+// and is the staple term of both, so summing 1 - Re Tr(U T^+)/6 over the
+// bonds and staple directions (T = T+ + T-, two plaquettes) counts each
+// plaquette's 1 - Re Tr/3 once.  A finished stage makes the launch a no-op.
+__global__ void __launch_bounds__(256) k_ape(Geo g, const double* __restrict__ Uold, double* __restrict__ Unew,
+                                             size_t cs, int d, double c, BondClasses bc,
+                                             const ApeState* __restrict__ st, double* __restrict__ bsum)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (st->done) return;
+    const int per = g.Vh >> 2;  // V / 8
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    if (e < 2 * g.Vh) {
-        const int par = e >= g.Vh ? 1 : 0;
+    if (t < bc.n * per) {
+        const int k = t / per;
+        const int mu = bc.mu[k];
         int n[4];
-        cb_coords(g, e - par * g.Vh, par, n);
-        const Links<double, 18> U{ (uintptr_t)Ud, cs };
-        for (int mu = 0; mu < 4; mu++)
-            for (int nu = mu + 1; nu < 4; nu++) {
-                if (n_odd_excl(n, mu, nu) != d) continue;
-                int npm[4] = { n[0], n[1], n[2], n[3] }, npn[4] = { n[0], n[1], n[2], n[3] };
-                npm[mu] = wrap_add(n[mu], 1, g.L[mu]);
-                npn[nu] = wrap_add(n[nu], 1, g.L[nu]);
-                const M3<double> X = m_mul(load_at(U, g, mu, n), load_at(U, g, nu, npm));
-                const M3<double> Y = m_mul(load_at(U, g, nu, n), load_at(U, g, mu, npn));
-                acc += 1.0 - retr_nd(X, Y) / 3.0;
+        class_site(g, 1 << mu, bc.odd[k], t - k * per, n);
+        const Links<double, 18> U{ (uintptr_t)Uold, cs };
+        const M3<double> u = load_at(U, g, mu, n);
+        // M = U + c (T+ + T-) added direction by direction, nu ascending
+        M3<double> M = u;
+        for (int nu = 0; nu < 4; nu++) {
+            if (nu == mu || n_odd_excl(n, mu, nu) != d) continue;
+            int npn[4] = { n[0], n[1], n[2], n[3] }, npm[4] = { n[0], n[1], n[2], n[3] },
+                nmn[4] = { n[0], n[1], n[2], n[3] };
+            npn[nu] = wrap_add(n[nu], 1, g.L[nu]);
+            npm[mu] = wrap_add(n[mu], 1, g.L[mu]);
+            nmn[nu] = wrap_add(n[nu], -1, g.L[nu]);
+            int nmn_pm[4] = { nmn[0], nmn[1], nmn[2], nmn[3] };
+            nmn_pm[mu] = npm[mu];
+            // T+ = U_nu(n) U_mu(n+nu) U_nu(n+mu)^+
+            M3<double> T = m_mul_nd(m_mul(load_at(U, g, nu, n), load_at(U, g, mu, npn)), load_at(U, g, nu, npm));
+            // T- = U_nu(n-nu)^+ U_mu(n-nu) U_nu(n-nu+mu)
+            m_acc(T, m_mul(m_mul_dn(load_at(U, g, nu, nmn), load_at(U, g, mu, nmn)), load_at(U, g, nu, nmn_pm)));
+            acc += 1.0 - retr_nd(u, T) / 6.0;
+#pragma unroll
+            for (int k2 = 0; k2 < 9; k2++) {
+                M.re[k2] += T.re[k2] * c;
+                M.im[k2] += T.im[k2] * c;
             }
+        }
+        const int par = (n[0] + n[1] + n[2] + n[3]) & 1;
+        store_link<double, 18>((uintptr_t)Unew + (uintptr_t)(mu * 2 + par) * cs, lex_index(g, n) >> 1,
+                               project_su3(M));
     }
     acc = block_sum_256p(acc);
     if (threadIdx.x == 0) bsum[blockIdx.x] = acc;
+}
+
+// After step j: S_d of iterate j-1 from the block sums (each thread a strided
+// share in block order, then a fixed tree); step j-1 ends the stage when S_d
+// changed by no more than rel_tol relative to iterate j-2, else step j ends
+// it when j = max_iter.
+__global__ void __launch_bounds__(256) k_ape_check(const double* __restrict__ bsum, int nblk, ApeState* st, int j,
+                                                   double rel_tol, int max_iter)
+{
+    if (st->done) return;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) v += bsum[b];
+    v = block_sum_256p(v);
+    if (threadIdx.x == 0) {
+        if (j >= 2 && fabs(v - st->s_prev) <= rel_tol * st->s_prev) {
+            st->done = 1;
+            st->iters = j - 1;
+        } else if (j >= max_iter) {
+            st->done = 1;
+            st->iters = j;
+        }
+        st->s_prev = v;
+    }
+}
+
+__global__ void k_ape_reset(ApeState* st)
+{
+    st->s_prev = 0.0;
+    st->done = 0;
+    st->iters = 0;
 }
 
 template <typename RF, int NF>
@@ -229,18 +287,52 @@ hipError_t launch_transfer(int pc, const Geo& gc, const void* Uc, size_t csc, co
     return hipGetLastError();
 }
 
-hipError_t launch_ape(const Geo& gf, const double* Uold, double* Unew, size_t csf, int d, double c, hipStream_t st)
+static BondClasses bond_classes(int d)
 {
-    const int nb = (8 * gf.Vh + 255) / 256;
-    k_ape<<<nb, 256, 0, st>>>(gf, Uold, Unew, csf, d, c);
+    BondClasses bc;
+    bc.n = 0;
+    for (int mu = 0; mu < 4; mu++)
+        for (int odd = 0; odd < 16; odd++)
+            if (!((odd >> mu) & 1) && __builtin_popcount(odd) == d + 1) {
+                bc.mu[bc.n] = mu;
+                bc.odd[bc.n] = odd;
+                bc.n++;
+            }
+    return bc;
+}
+
+int ape_blocks(const Geo& gf, int d)
+{
+    return (int)(((long long)bond_classes(d).n * (gf.Vh >> 2) + 255) / 256);
+}
+
+size_t ape_state_bytes() { return sizeof(ApeState); }
+
+hipError_t launch_ape_reset(void* state, hipStream_t st)
+{
+    k_ape_reset<<<1, 1, 0, st>>>((ApeState*)state);
     return hipGetLastError();
 }
 
-hipError_t launch_partial_action(const Geo& gf, const double* U, size_t csf, int d, double* block_sums, int nblk,
-                                 hipStream_t st)
+hipError_t launch_ape_step(const Geo& gf, const double* Uold, double* Unew, size_t csf, int d, double c, int j,
+                           double rel_tol, int max_iter, void* state, double* block_sums, int nblk, hipStream_t st)
 {
-    k_partial_action<<<nblk, 256, 0, st>>>(gf, U, csf, d, block_sums);
+    for (int m = 0; m < 4; m++)
+        if (gf.L[m] & 1) return hipErrorInvalidValue;
+    if (nblk != ape_blocks(gf, d) || nblk == 0) return hipErrorInvalidValue;
+    k_ape<<<nblk, 256, 0, st>>>(gf, Uold, Unew, csf, d, c, bond_classes(d), (const ApeState*)state, block_sums);
+    k_ape_check<<<1, 256, 0, st>>>(block_sums, nblk, (ApeState*)state, j, rel_tol, max_iter);
     return hipGetLastError();
+}
+
+hipError_t read_ape_state(const void* state, int* done, int* iters, hipStream_t st)
+{
+    ApeState h;
+    hipError_t e = hipMemcpyAsync(&h, state, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    *done = h.done;
+    *iters = h.iters;
+    return e;
 }
 
 }  // namespace msmc

@@ -152,9 +152,15 @@ hipError_t launch_restrict(int pf, const Geo& gf, const void* Uf, size_t csf, in
                            size_t csc, hipStream_t st);
 hipError_t launch_transfer(int pc, const Geo& gc, const void* Uc, size_t csc, const Geo& gf, double* Uf,
                            size_t csf, hipStream_t st);
-hipError_t launch_ape(const Geo& gf, const double* Uold, double* Unew, size_t csf, int d, double c,
-                      hipStream_t st);
-hipError_t launch_partial_action(const Geo& gf, const double* U, size_t csf, int d, double* block_sums, int nblk,
-                                 hipStream_t st);
+// One interpolation step j of stage d (Uold = iterate j-1 -> Unew = iterate j)
+// plus the device-side stopping rule; state (ape_state_bytes() bytes) is
+// reset at the stage start, block_sums holds ape_blocks(gf, d) doubles.
+int ape_blocks(const Geo& gf, int d);
+size_t ape_state_bytes();
+hipError_t launch_ape_reset(void* state, hipStream_t st);
+hipError_t launch_ape_step(const Geo& gf, const double* Uold, double* Unew, size_t csf, int d, double c, int j,
+                           double rel_tol, int max_iter, void* state, double* block_sums, int nblk, hipStream_t st);
+// waits for the stream, then reads whether the stage is done and its step count
+hipError_t read_ape_state(const void* state, int* done, int* iters, hipStream_t st);
 
 }  // namespace msmc

@@ -340,9 +340,9 @@ def test_adaptive_flow_matches_oracle(m, orc, prec):
     assert abs(m.su3_flow_t0(tt, EE, 0.3) - orc.flow_t0(tt, EE, 0.3)) < 1e-15
 
 
-def test_restrict_and_prolongate_match_oracle(m, orc):
-    dc = [2, 4, 2, 2]
-    df = [4, 8, 4, 4]
+@pytest.mark.parametrize("dc", [[2, 4, 2, 2], [4, 2, 6, 2]])
+def test_restrict_and_prolongate_match_oracle(m, orc, dc):
+    df = [2 * x for x in dc]
     Uc = orc.init_hot(dc, 7, 0)
     orc.sweep_hb_or(dc, Uc, 5.8, 7, 0, 0, 10)
     c = field(m, dc)
