@@ -467,10 +467,12 @@ __device__ __forceinline__ double su2_part_c(const M3<double>& W, int i, int j, 
     const double x2 = (W.re[ij] - W.re[ji]) * 0.5;
     const double k = sqrt(x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
     if (k == 0.0) return 0.0;
-    v[0][0] = Cx{ x0 / k, x3 / k };
-    v[0][1] = Cx{ x2 / k, x1 / k };
-    v[1][0] = Cx{ -x2 / k, x1 / k };
-    v[1][1] = Cx{ x0 / k, -x3 / k };
+    // four quotients; negating one equals dividing the negated numerator
+    const double q0 = x0 / k, q1 = x1 / k, q2 = x2 / k, q3 = x3 / k;
+    v[0][0] = Cx{ q0, q3 };
+    v[0][1] = Cx{ q2, q1 };
+    v[1][0] = Cx{ -q2, q1 };
+    v[1][1] = Cx{ q0, -q3 };
     return k;
 }
 

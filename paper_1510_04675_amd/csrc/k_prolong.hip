@@ -119,9 +119,11 @@ __device__ M3<double> project_su3(const M3<double>& M)
 // The bonds a stage updates, grouped in classes: a direction mu and the set
 // of other coordinates that are odd (a bit mask, bit m for coordinate m).
 // Each class holds V/8 sites: n_mu takes every value, each other coordinate
-// the values of its parity.  Thread t maps to class t / (V/8) and to a site
-// of that class, coordinate 0 fastest, so that a wavefront reads consecutive
-// checkerboard sites.
+// the values of its parity, numbered with coordinate 0 fastest so that a
+// wavefront reads consecutive checkerboard sites.  A block takes 256
+// consecutive sites of one class; blocks run chunk-major and class-minor,
+// renumbered so that each XCD gets a contiguous range, so the classes of one
+// region of the lattice are updated together and share its links in L2.
 struct BondClasses {
     int n;
     int mu[12];
@@ -180,13 +182,14 @@ __global__ void __launch_bounds__(256) k_ape(Geo g, const double* __restrict__ U
 {
     if (st->done) return;
     const int per = g.Vh >> 2;  // V / 8
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lb = logical_block(blockIdx.x, gridDim.x, 1);
+    const int k = lb % bc.n;
+    const int r = (lb / bc.n) * 256 + threadIdx.x;
     double acc = 0.0;
-    if (t < bc.n * per) {
-        const int k = t / per;
+    if (r < per) {
         const int mu = bc.mu[k];
         int n[4];
-        class_site(g, 1 << mu, bc.odd[k], t - k * per, n);
+        class_site(g, 1 << mu, bc.odd[k], r, n);
         const Links<double, 18> U{ (uintptr_t)Uold, cs };
         const M3<double> u = load_at(U, g, mu, n);
         // M = U + c (T+ + T-) added direction by direction, nu ascending
@@ -303,7 +306,7 @@ static BondClasses bond_classes(int d)
 
 int ape_blocks(const Geo& gf, int d)
 {
-    return (int)(((long long)bond_classes(d).n * (gf.Vh >> 2) + 255) / 256);
+    return bond_classes(d).n * (((gf.Vh >> 2) + 255) / 256);
 }
 
 size_t ape_state_bytes() { return sizeof(ApeState); }
