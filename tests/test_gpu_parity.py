@@ -358,6 +358,25 @@ def test_restrict_and_prolongate_match_oracle(m, orc, dc):
     assert np.max(np.abs(m.su3_field_to_host(c2) - Uc)) < 1e-14
 
 
+@pytest.mark.parametrize("rel_tol,max_iter", [(1e-5, 1), (1e-5, 3), (0.0, 17), (1e-5, 0)])
+def test_prolongate_step_caps_match_oracle(m, orc, rel_tol, max_iter):
+    """Stopping by the step cap (1, 3, and 17: past a run of 16 enqueued steps),
+    a tolerance that never stops early, and no steps at all: step counts and
+    links as the oracle's."""
+    dc = [2, 2, 4, 2]
+    df = [2 * x for x in dc]
+    Uc = orc.init_hot(dc, 5, 0)
+    orc.sweep_hb_or(dc, Uc, 5.8, 5, 0, 0, 4)
+    c = field(m, dc)
+    fine = field(m, df)
+    m.su3_field_from_host(c, Uc)
+    it = m.su3_prolongate(c, fine, 0.05, rel_tol, max_iter)
+    Uf, rit = orc.prolongate(dc, Uc, 0.05, rel_tol, max_iter)
+    assert list(it) == list(rit)
+    assert all(k <= max_iter for k in it)
+    assert np.max(np.abs(m.su3_field_to_host(fine) - Uf)) < 1e-11
+
+
 def test_check_field_flags_bad_links(m, orc):
     d = [4, 4, 4, 4]
     U = orc.init_hot(d, 1, 0)
