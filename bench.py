@@ -327,7 +327,7 @@ def main():
     ap.add_argument("--launch", default="", help="fix the launch shape block,xcd_remap,ty,tz,tt (implies --no-tune)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(independent lattices would shard across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
     import torch

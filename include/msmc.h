@@ -53,7 +53,7 @@ enum su3_status {
     SU3_ERR_NOMEM = 3,       /* device allocation failed */
     SU3_ERR_HIP = 4,         /* a HIP runtime call failed */
     SU3_ERR_NUMERIC = 5,     /* a link is not in SU(3) within tolerance, or NaN */
-    SU3_ERR_UNSUPPORTED = 6  /* valid request this build does not implement */
+    SU3_ERR_UNSUPPORTED = 6  /* valid request the library does not implement */
 };
 
 /* Link storage precision.  SU3_FP32_R12 stores rows 0 and 1 only and
