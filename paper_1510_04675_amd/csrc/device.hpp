@@ -501,6 +501,23 @@ __device__ __forceinline__ void mul2_c(const Cx a[2][2], const Cx b[2][2], Cx c[
         for (int q = 0; q < 2; q++) c[p][q] = c_add(c_mul(a[p][0], b[0][q]), c_mul(a[p][1], b[1][q]));
 }
 
+// Rows 0 and 1 made orthonormal for a 12-real store, computed in fp64 and
+// rounded once.  An fp32 Gram-Schmidt without contracted arithmetic leaves the
+// row norms off by a fraction of an ulp with the same sign on every link;
+// summed over millions of links that shifts the action by whole units (one
+// 32^4 HMC trajectory gave an energy difference of 13.3 where fp64 gives
+// 9.45), whereas a single rounding of exact rows is unbiased.
+template <typename R> __device__ __forceinline__ void m_reunit_for_store(M3<R>& a)
+{
+    if constexpr (std::is_same<R, double>::value) {
+        m_reunit(a);
+    } else {
+        M3<double> d = m_cast<R, double>(a);
+        m_reunit(d);
+        a = m_cast<double, R>(d);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Link field views.
 // ---------------------------------------------------------------------------
@@ -730,16 +747,19 @@ __device__ __forceinline__ int logical_block(int b, int nblocks, int remap)
 
 // Exponential of an anti-hermitian traceless 3x3 matrix X: Taylor series of
 // X / 2^s (Horner, order N) followed by s squarings, with s chosen so that
-// the Frobenius norm of X / 2^s is at most 1/4.
-template <typename R, int N> __device__ __forceinline__ M3<R> m_exp_ah(const M3<R>& X)
+// the Frobenius norm of X / 2^s is at most 2^-L (the remainder is then below
+// 2^(-L (N+1)) / (N+1)!).  The innermost Horner factor 1 + Y/N is formed
+// directly, so order N costs N - 1 matrix products.
+template <typename R, int N, int L = 2> __device__ __forceinline__ M3<R> m_exp_ah(const M3<R>& X)
 {
     R nrm = R(0);
 #pragma unroll
     for (int k = 0; k < 9; k++) nrm += X.re[k] * X.re[k] + X.im[k] * X.im[k];
     nrm = m_sqrt(nrm);
+    const R lim = R(1) / R(1 << L);
     int s = 0;
     R sc = R(1);
-    while (nrm * sc > R(0.25) && s < 40) {
+    while (nrm * sc > lim && s < 40) {
         sc *= R(0.5);
         s++;
     }
@@ -751,9 +771,19 @@ template <typename R, int N> __device__ __forceinline__ M3<R> m_exp_ah(const M3<
     }
     // Horner: E = 1 + Y (1 + Y/2 (1 + Y/3 (... (1 + Y/N))))
     M3<R> E;
-    m_set_one(E);
+    {
+        const R f = R(1) / R(N);
 #pragma unroll
-    for (int k = N; k >= 1; k--) {
+        for (int q = 0; q < 9; q++) {
+            E.re[q] = Y.re[q] * f;
+            E.im[q] = Y.im[q] * f;
+        }
+        E.re[0] += R(1);
+        E.re[4] += R(1);
+        E.re[8] += R(1);
+    }
+#pragma unroll
+    for (int k = N - 1; k >= 1; k--) {
         M3<R> T = m_mul(Y, E);
         const R f = R(1) / R(k);
 #pragma unroll

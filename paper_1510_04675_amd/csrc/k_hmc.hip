@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(Grid gr, double eps_kick, do
         M3<R> un = m_mul(E, u);
         // 12-real records: row 2 is rebuilt from rows 0 and 1, so keep them
         // orthonormal (their rounding would otherwise feed back).
-        if constexpr (NC == 12) m_reunit(un);
+        if constexpr (NC == 12) m_reunit_for_store(un);
         store_link<R, NC>(D.slab(x.mu, x.par), x.cb, un);
     }
 }

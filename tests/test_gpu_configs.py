@@ -171,8 +171,11 @@ def test_config3_multiscale_step(m, orc):
     print("C3 stage times (s): " + ", ".join(f"{k} {v:.3f}" for k, v in times.items()))
     assert d64 < 1e-10
     assert abs(p_64 - p_ref) < 1e-12 and abs(q_64 - q_ref) < 1e-9
-    assert abs(p_r12 - p_ref) < 1e-6
-    assert abs(q_r12 - q_ref) < 1e-3
+    # R12 stores are re-orthonormalized in fp64 and rounded once, so the
+    # flowed plaquette carries only rounding noise (about 1e-9 here; an fp32
+    # Gram-Schmidt shifted it by 2e-7 through a sign-consistent norm bias)
+    assert abs(p_r12 - p_ref) < 2e-8
+    assert abs(q_r12 - q_ref) < 1e-4
 
 
 def c4_lattices(m, prec):

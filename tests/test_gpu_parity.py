@@ -297,6 +297,30 @@ def test_hmc_fp32_dh_tracks_fp64(m, orc):
     assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 5e-4
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp32_r12"])
+def test_hmc_reduced_precision_dh_at_16_4(m, prec):
+    """One 40-step trajectory on a thermalized 16^4 lattice in reduced
+    precision against fp64 from the same links (fp64 is pinned to the oracle
+    by the tests above).  dH is a difference of actions summed over 393216
+    links, so a per-link bias of a fraction of an fp32 ulp in the stored links
+    shows up here (an fp32 Gram-Schmidt in the 12-real drift gave 0.85 against
+    0.61); rounding noise alone stays near 0.01."""
+    d = [16] * 4
+    f = field(m, d, prec)
+    m.su3_init_cold(f)
+    m.su3_sweep_hb_or(f, 6.0, 5, 0, 0, 30, m.hb_params(n_or=4, reunit_every=10), record=False)
+    g = field(m, d, "fp64")
+    m.su3_field_copy(g, f)
+    _, dh = m.su3_hmc_trajectory(f, 6.0, 1.0, 40, 5, 0, 7, 0)
+    _, dh64 = m.su3_hmc_trajectory(g, 6.0, 1.0, 40, 5, 0, 7, 0)
+    h = field(m, d, "fp64")
+    m.su3_field_copy(h, f)
+    p_end, p64_end = m.su3_plaquette(f), m.su3_plaquette(h)
+    print(f"\n{prec} 16^4 dH {dh:.5f} vs fp64 {dh64:.5f}; end plaquette {p_end:.10f} vs its fp64 copy {p64_end:.10f}")
+    assert abs(dh - dh64) < 0.05, (dh, dh64)
+    assert abs(p_end - p64_end) < 5e-9, (p_end, p64_end)
+
+
 def test_wilson_flow_matches_oracle(m, orc):
     d = [4, 4, 6, 4]
     U = orc.init_hot(d, 3, 0)
