@@ -153,7 +153,10 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
  * fp64; kick-drift-kick leapfrog with eps = tau / n_steps, U <- exp(i eps P)
  * U, in the storage precision; Metropolis with the uniform of Philox purpose
  * ACCEPT (site word 0) against exp(-dH).  metropolis = 0 accepts always
- * (warm-up trajectories).  On rejection the field is unchanged. */
+ * (warm-up trajectories).  On rejection the field is unchanged.  12-real
+ * links are re-orthonormalized (in fp64, rounded once) at every drift store;
+ * 18-real fp32 links are not, so their distance from SU(3) grows slowly over
+ * many trajectories: long runs call su3_reunitarize between trajectories. */
 int32_t su3_hmc_trajectory(su3_field f, double beta, double tau, int32_t n_steps, uint32_t seed,
                            uint32_t lattice_id, uint64_t traj, int32_t metropolis, double* dH, int32_t* accepted);
 
