@@ -364,6 +364,11 @@ def main():
         log("bench: hmc (32^4, tau 1, 40 steps, 20 trajectories) ...")
         hmc = run_hmc(m, torch, dims)
         log(f"bench: hmc {hmc['trajectories_per_s']} traj/s, acceptance {hmc['acceptance']}")
+        # the same run with 12-real links (re-orthonormalized at every drift)
+        r12 = run_hmc(m, torch, dims, prec="fp32_r12")
+        hmc["fp32_r12_links"] = {k: r12[k] for k in ("trajectories_per_s", "acceptance", "mean_dH", "dH_same_start")}
+        log(f"bench: hmc r12 {r12['trajectories_per_s']} traj/s, dH vs fp64 from the same start "
+            f"{r12['dH_same_start']['abs_dev']:.2e}")
     ms = None
     if not a.no_multiscale and (not a.only or "multiscale" in want):
         log("bench: multiscale (16^4 -> 32^4 prolongation, displaced loops) ...")

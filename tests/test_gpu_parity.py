@@ -333,12 +333,12 @@ def test_wilson_flow_matches_oracle(m, orc):
     assert abs(m.su3_topological_charge(f) - orc.topological_charge(d, U)) < 1e-11
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32_r12"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_r12"])
 def test_adaptive_flow_matches_oracle(m, orc, prec):
     """Adaptive-step flow (tolerance 0.01, maximum step 0.2, first step 0.2
     so that rejections occur): FP64 takes the oracle's accepted and rejected
     steps and matches E, Q at the measurement times and the final links;
-    R12 matches E to 1e-6 relative.  Admissibility h and the t0
+    FP32 and R12 match E to 1e-6 relative.  Admissibility h and the t0
     interpolation against the oracle on the same data."""
     d = [6, 4, 8, 6]
     U = orc.init_hot(d, 17, 0)
