@@ -322,6 +322,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-hmc", action="store_true", help="skip the HMC report")
+    ap.add_argument("--no-hmc-r12", action="store_true", help="skip the HMC run with 12-real links")
     ap.add_argument("--no-multiscale", action="store_true", help="skip the prolongation / displaced-loop report")
     ap.add_argument("--no-batch48", action="store_true", help="skip the 48-lattice batched run")
     ap.add_argument("--launch", default="", help="fix the launch shape block,xcd_remap,ty,tz,tt (implies --no-tune)")
@@ -364,11 +365,13 @@ def main():
         log("bench: hmc (32^4, tau 1, 40 steps, 20 trajectories) ...")
         hmc = run_hmc(m, torch, dims)
         log(f"bench: hmc {hmc['trajectories_per_s']} traj/s, acceptance {hmc['acceptance']}")
-        # the same run with 12-real links (re-orthonormalized at every drift)
-        r12 = run_hmc(m, torch, dims, prec="fp32_r12")
-        hmc["fp32_r12_links"] = {k: r12[k] for k in ("trajectories_per_s", "acceptance", "mean_dH", "dH_same_start")}
-        log(f"bench: hmc r12 {r12['trajectories_per_s']} traj/s, dH vs fp64 from the same start "
-            f"{r12['dH_same_start']['abs_dev']:.2e}")
+        if not a.no_hmc_r12:
+            # the same run with 12-real links (re-orthonormalized at every drift)
+            r12 = run_hmc(m, torch, dims, prec="fp32_r12")
+            hmc["fp32_r12_links"] = {k: r12[k] for k in ("trajectories_per_s", "acceptance", "mean_dH",
+                                                          "dH_same_start")}
+            log(f"bench: hmc r12 {r12['trajectories_per_s']} traj/s, dH vs fp64 from the same start "
+                f"{r12['dH_same_start']['abs_dev']:.2e}")
     ms = None
     if not a.no_multiscale and (not a.only or "multiscale" in want):
         log("bench: multiscale (16^4 -> 32^4 prolongation, displaced loops) ...")
