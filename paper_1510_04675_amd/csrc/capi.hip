@@ -707,6 +707,17 @@ static int32_t single_plan(su3_field_s* f, int out_cap)
     return SU3_OK;
 }
 
+// Descriptor of f carrying its plan's launch tile (single_plan must have run):
+// the link walks of the HMC and flow kernels then follow the tuned or forced
+// tile, like the phase kernels.
+static LatDesc plan_desc(const su3_field_s* f)
+{
+    LatDesc d = base_desc(f);
+    if (!f->plan.host_descs.empty())
+        for (int k = 0; k < 3; k++) d.tile[k] = f->plan.host_descs[0].tile[k];
+    return d;
+}
+
 static int32_t ensure_scratch(su3_field_s* f, bool alts, bool aux, int n_alts = 2)
 {
     if (alts) {
@@ -1267,7 +1278,7 @@ int32_t su3_hmc_trajectory(su3_field f, double beta, double tau, int32_t n_steps
     Plan& p = f->plan;
     hipStream_t st = f->stream;
     // descriptor variants: 0: U -> alt0, 1: alt0 -> alt1, 2: alt1 -> alt0
-    std::vector<LatDesc> d(3, base_desc(f));
+    std::vector<LatDesc> d(3, plan_desc(f));
     for (auto& x : d) {
         x.beta = beta;
         x.seed = seed;
@@ -1335,7 +1346,7 @@ int32_t su3_wilson_flow(su3_field f, double eps, int32_t n_steps)
     if ((rc = ensure_scratch(f, true, true))) return rc;
     if ((rc = single_plan(f, 1))) return rc;
     hipStream_t st = f->stream;
-    std::vector<LatDesc> d(2, base_desc(f));
+    std::vector<LatDesc> d(2, plan_desc(f));
     d[0].U = f->data;
     d[0].aux2 = f->alt[0];
     d[1].U = f->alt[0];
@@ -1393,7 +1404,7 @@ int32_t su3_wilson_flow_adaptive(su3_field f, double t_end, double tol, double m
     // (configuration 1); alt1 holds W2, alt2 the embedded W~.
     void* w0b[2] = { f->data, f->alt[0] };
     void* oth[2] = { f->alt[0], f->data };
-    std::vector<LatDesc> d(6, base_desc(f));
+    std::vector<LatDesc> d(6, plan_desc(f));
     for (int c = 0; c < 2; c++) {
         LatDesc* x = &d[3 * c];
         for (int k = 0; k < 3; k++) {

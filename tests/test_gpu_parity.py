@@ -203,8 +203,9 @@ def test_fp32_sweeps_track_fp64_oracle(m, orc, prec):
 
 
 def test_launch_shape_and_resume_invariance(m, orc):
-    """Bitwise identical results for every phase-kernel launch shape, and N
-    sweeps equal N/2 + N/2 sweeps."""
+    """Bitwise identical results for every launch shape (phase kernels, and
+    the link walks of an HMC trajectory and of a flow), and N sweeps equal
+    N/2 + N/2 sweeps."""
     d = [8, 6, 4, 4]
     ref = None
     shapes = [(64, 0, (0, 0, 1)), (128, 1, (2, 2, 2)), (256, 1, (3, 4, 4)), (512, 0, (6, 2, 1)), (512, 1, (16, 8, 4)),
@@ -218,9 +219,15 @@ def test_launch_shape_and_resume_invariance(m, orc):
             m.su3_sweep_hb_or(f, 6.0, 6, 1, 0, 2, P(n_or=2))
             m.su3_sweep_hb_or(f, 6.0, 6, 1, 2, 2, P(n_or=2))
             U = m.su3_field_to_host(f)
+            h = field(m, d, "fp32_r12")
+            m.su3_field_copy(h, f)
+            _, dh = m.su3_hmc_trajectory(h, 6.0, 1.0, 6, 6, 1, 3, 0)
+            m.su3_wilson_flow(h, 0.02, 3)
+            H = (dh, m.su3_field_to_host(h))
             if ref is None:
-                ref = U
+                ref, href = U, H
             assert np.array_equal(U, ref), (block, remap, tile)
+            assert H[0] == href[0] and np.array_equal(H[1], href[1]), (block, remap, tile)
     finally:
         m.su3_set_launch(0, 1)
         m.su3_set_tile(0, 0, 0)
