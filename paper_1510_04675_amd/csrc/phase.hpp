@@ -176,11 +176,31 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
     store_link<R, NC, true>(s, cb, u);
 }
 
+// Overrelaxation phases keep at most 12 wavefronts per CU in flight: with
+// more, the links of their sites and neighbours overflow the XCD's 4 MB L2
+// before the other readers of a record run (a 32^4 R12 phase took 47.0 us at
+// 20 wavefronts per CU and 45.0 us at 12; 8 and 16 were slower, and the heat
+// bath, with more arithmetic per load, is faster uncapped).  The cap reserves
+// LDS per block, which the kernel does not use: 144 KB shared by the blocks
+// allowed (three blocks of 54.5 KB did not fit together on a CU, three of 48
+// KB did).  Blocks of 512 threads are left alone (a cap there would exceed 64
+// KB per block).
+constexpr int kOrWavesPerCu = 12;
+
+static size_t or_lds_bytes(int block)
+{
+    const int waves = block / 64;
+    if (waves < 1 || waves > 4) return 0;
+    const int blocks_per_cu = kOrWavesPerCu / waves;
+    return (size_t)(147456 / blocks_per_cu) & ~(size_t)255;
+}
+
 template <typename R, int NC, int KIND>
 static hipError_t launch_phase_t(const Grid& gr, int mu, int par, const uint64_t* sb, int so, HbArgs hb,
                                  unsigned long long* ex, hipStream_t st)
 {
-    k_phase<R, NC, KIND><<<gr.nblocks, gr.block, 0, st>>>(gr, mu, par, sb, so, hb, ex);
+    const size_t lds = (KIND == 1) ? or_lds_bytes(gr.block) : 0;
+    k_phase<R, NC, KIND><<<gr.nblocks, gr.block, lds, st>>>(gr, mu, par, sb, so, hb, ex);
     return hipGetLastError();
 }
 
