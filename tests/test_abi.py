@@ -53,3 +53,25 @@ def test_null_handles_are_rejected():
     assert L.su3_set_launch(100, 1) == 1
     assert L.su3_profile_read(3, None, None) == 1
     assert L.su3_batch_sweep_hb_or(None, 0, None, None, None, 0, 1, None, None) == 1
+
+
+def test_host_only_entry_points_validate_and_compute():
+    """Calls that do no device work run without a GPU: t0 interpolation
+    against the oracle's, its error cases, and the setters' argument checks."""
+    import numpy as np
+    import oracle as orc
+    from paper_1510_04675_amd import capi
+    tt = np.linspace(0.1, 2.0, 20)
+    EE = (0.05 + 0.2 * tt) / tt**2  # t^2 E = 0.05 + 0.2 t crosses 0.3 at t = 1.25
+    t0 = capi.su3_flow_t0(tt, EE, 0.3)
+    assert abs(t0 - orc.flow_t0(tt, EE, 0.3)) < 1e-15
+    assert abs(t0 - 1.25) < 1e-12  # t^2 E is linear in t here, so the interpolation is exact
+    with pytest.raises(capi.SU3Error) as e:
+        capi.su3_flow_t0(tt, EE, 5.0)  # never reached
+    assert e.value.code == 5
+    L = capi.lib()
+    assert L.su3_set_tile(-1, 2, 2) == 1
+    assert L.su3_set_tile(0, 0, 0) == 0
+    assert L.su3_set_launch(0, 2) == 1
+    assert L.su3_set_launch(0, 1) == 0
+    assert L.su3_set_group_bytes(224 << 20) == 0
