@@ -237,6 +237,31 @@ def test_launch_shape_and_resume_invariance(m, orc):
     assert np.array_equal(m.su3_field_to_host(f), ref)
 
 
+def test_autotuned_shape_is_a_candidate_and_changes_nothing(m, orc):
+    """The first sweep call on a new shape with the autotuner on picks one of
+    the candidate launch shapes (block 128/256/512, remap 0/1, one of seven
+    tiles) for that shape and leaves the results bitwise those of the default
+    shape; the oracle agrees on the FP64 field."""
+    d = [6, 8, 4, 4]
+    U0 = orc.init_hot(d, 21, 0)
+    res = {}
+    try:
+        for tuned in (False, True):
+            m.su3_autotune(tuned)
+            f = field(m, d)
+            m.su3_field_from_host(f, U0)
+            m.su3_sweep_hb_or(f, 6.0, 21, 0, 0, 2, P(n_or=2))
+            res[tuned] = (m.su3_field_to_host(f), m.su3_get_config([f]))
+    finally:
+        m.su3_autotune(False)
+    cfg = res[True][1]
+    assert cfg["block"] in (128, 256, 512) and cfg["xcd_remap"] in (0, 1), cfg
+    assert np.array_equal(res[True][0], res[False][0])
+    U = U0.copy()
+    orc.sweep_hb_or(d, U, 6.0, 21, 0, 0, 2, n_or=2)
+    assert np.max(np.abs(res[True][0] - U)) < 1e-12
+
+
 def test_batch_equals_separate_calls(m, orc):
     """One batched graph launch over lattices of uneven shapes gives bitwise
     the fields and plaquettes of separate calls, for any grouping of the
