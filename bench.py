@@ -203,6 +203,39 @@ def run_multiscale(m, torch, L=32, beta_c=5.7, beta=6.0, n_coarse=20, n_sweeps=2
     return out
 
 
+def run_flow(m, torch, L=32, n_steps=20, eps=0.02):
+    """Fixed-step RK3 Wilson flow (Sec. IV.B) of a thermalized L^4 lattice in
+    R12 and FP64: ms per flow step and the flow stage kernel against 8 TB/s.
+    Algorithmic bytes per link of one step: the first stage reads W and
+    writes W' and X (8 reals), the other two also read X; a link record is
+    rec bytes, so 3 (2 rec) + 8 r (1 + 2 + 2) with r the real size
+    (R12: 448 B, FP64: 1184 B); the staple neighbours are counted as the
+    field read once."""
+    out = {}
+    base = m.Field([L] * 4, "fp32_r12")
+    m.su3_init_cold(base)
+    m.su3_sweep_hb_or(base, 6.0, 9, 0, 0, 50, m.hb_params(n_or=4, reunit_every=10), record=False)
+    for prec, rec, r in (("fp32_r12", 48, 4), ("fp64", 144, 8)):
+        f = m.Field([L] * 4, prec)
+        m.su3_field_copy(f, base)
+        m.su3_wilson_flow(f, eps, 1)  # allocates the flow buffers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.su3_wilson_flow(f, eps, n_steps)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / n_steps
+        links = 4 * L ** 4
+        alg = links * (3 * 2 * rec + 8 * r * 5)
+        out[prec] = {"ms_per_step": round(ms, 4), "algorithmic_bytes_per_step": alg,
+                     "achieved_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_8TBps": round(alg / (ms * 1e-3) / 8e12, 4),
+                     "plaquette_after": m.su3_plaquette(f), "Q_after": m.su3_topological_charge(f)}
+        f.close()
+    base.close()
+    out["flow"] = f"{n_steps} RK3 steps of eps {eps} from a {L}^4 lattice (cold start + 50 R12 sweeps at beta 6.0)"
+    return out
+
+
 def run_batch48(m, torch, prec="fp32", n_sweeps=100):
     """48 prolongated lattices of uneven sizes (16 each of 12^4, 16^4, 20^4),
     beta_i uniform in [5.9, 6.2] (numpy PCG64 seed 4), coarse (L/2)^4 hot
@@ -325,6 +358,7 @@ def main():
     ap.add_argument("--no-hmc-r12", action="store_true", help="skip the HMC run with 12-real links")
     ap.add_argument("--no-multiscale", action="store_true", help="skip the prolongation / displaced-loop report")
     ap.add_argument("--no-batch48", action="store_true", help="skip the 48-lattice batched run")
+    ap.add_argument("--no-flow", action="store_true", help="skip the Wilson flow report")
     ap.add_argument("--launch", default="", help="fix the launch shape block,xcd_remap,ty,tz,tt (implies --no-tune)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -377,13 +411,19 @@ def main():
         log("bench: multiscale (16^4 -> 32^4 prolongation, displaced loops) ...")
         ms = run_multiscale(m, torch, L)
         log(f"bench: prolongation {ms['prolongation_ms']} ms, displaced spread {ms['displaced_spread_vs_sweeps']}")
+    fl = None
+    if not a.no_flow and (not a.only or "flow" in want):
+        log("bench: Wilson flow (32^4, R12 and FP64, 20 RK3 steps) ...")
+        fl = run_flow(m, torch, L)
+        log("bench: flow " + ", ".join(f"{k} {v['ms_per_step']} ms/step ({v['frac_of_8TBps']:.2f} of 8 TB/s)"
+                                       for k, v in fl.items() if isinstance(v, dict)))
     b48 = None
     if not a.no_batch48 and (not a.only or "batch48" in want):
         log("bench: 48 prolongated lattices (12^4, 16^4, 20^4), 100 sweeps in one graph ...")
         b48 = {prec: run_batch48(m, torch, prec) for prec in ("fp32", "fp32_r12")}
         log("bench: batch48 " + ", ".join(f"{k} {v['link_updates_per_s']:.3e} link updates/s" for k, v in b48.items()))
     if head is None:  # only the HMC / multiscale / batch48 parts were asked for
-        print(json.dumps({"hmc": hmc, "multiscale": ms, "batch48": b48}), flush=True)
+        print(json.dumps({"hmc": hmc, "multiscale": ms, "flow": fl, "batch48": b48}), flush=True)
         return
     cpu = None
     if not a.no_cpu_baseline:
@@ -423,6 +463,8 @@ def main():
         line["hmc"] = hmc
     if ms is not None:
         line["multiscale"] = ms
+    if fl is not None:
+        line["flow"] = fl
     if b48 is not None:
         line["batch48"] = b48
     if "fp64" in res:
