@@ -126,7 +126,7 @@ int32_t su3_restrict(su3_field fine, su3_field coarse);
  * result is rounded into fine's precision.  Paper values: c = 0.05,
  * rel_tol = 1e-5 (Sec. IV.C).  iters_out (3 ints, may be NULL) receives
  * the steps taken per stage.  The call allocates and frees two fp64 copies of
- * the fine field and a few KB of block sums, applies the stopping rule on
+ * the fine field and block sums (8 bytes per 256 bonds), applies the rule on
  * the device (steps past the stopping point of a run of 16 do nothing) and
  * returns after the result is in fine.  c > 0, rel_tol >= 0 and
  * max_iter >= 0 (0: transfer only) or SU3_ERR_ARG; SU3_ERR_NOMEM if the
