@@ -330,6 +330,74 @@ def cpu_baseline(dims, threads, n_sweeps=4):
                       f"{threads} OpenMP threads, {dt:.1f} s"}
 
 
+def oracle_timing(threads_list=(1, 16)):
+    """The FP64 oracle (as it stands) on bounded samples of each workload
+    configuration, host only, at each thread count: measured seconds and the
+    full configuration extrapolated from the sample (per sweep for sweeps, per
+    step for the prolongation and the flow, by volume for HMC).  Prints one
+    progress line per item."""
+    import oracle
+
+    def cpu_model():
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+        except OSError:
+            pass
+        return "unknown"
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        r = fn()
+        return time.perf_counter() - t0, r
+
+    out = {"host": {"cpu": cpu_model(), "logical_cpus": os.cpu_count()}, "runs": []}
+    for th in threads_list:
+        oracle.set_threads(th)
+
+        def rec(config, sample, secs, full_secs, how):
+            out["runs"].append({"threads": th, "config": config, "sample": sample, "seconds": round(secs, 3),
+                                "full_config_seconds": round(full_secs, 1), "extrapolation": how})
+            log(f"bench: oracle {th} thread(s) {config}: {secs:.2f} s for {sample}; full config ~{full_secs:.1f} s")
+
+        d4, d8, d16 = [4] * 4, [8] * 4, [16] * 4
+        U = oracle.init_hot(d4, 1, 0)
+        t, _ = timed(lambda: oracle.sweep_hb_or(d4, U, 6.0, 1, 0, 0, 10, n_or=4))
+        rec("C1 4^4 FP64, 10 sweeps", "the whole configuration", t, t, "none")
+        U = oracle.init_cold(d16)
+        t, _ = timed(lambda: oracle.sweep_hb_or(d16, U, 6.0, 2, 0, 0, 5, n_or=4))
+        rec("C2 16^4 cold, 200 sweeps", "5 sweeps", t, t * 40, "x40 sweeps")
+        Uc = oracle.init_hot(d8, 7, 0)
+        t1, _ = timed(lambda: oracle.sweep_hb_or(d8, Uc, 5.8, 7, 0, 0, 100, n_or=4))
+        its = (156, 69, 39)  # steps the paper's tolerance takes on this input
+        t2, _ = timed(lambda: oracle.prolongate(d8, Uc, 0.05, 1e-5, 10))
+        Uf, _ = oracle.prolongate(d8, Uc, 0.05, 1e-5, 1)
+        t3, _ = timed(lambda: oracle.sweep_hb_or(d16, Uf, 6.0, 7, 0, 100, 5, n_or=4))
+        t4, _ = timed(lambda: oracle.wilson_flow(d16, Uf, 0.01, 5))
+        rec("C3 8^4 x 100 sweeps -> prolongation -> 16^4 x 50 sweeps -> 100 flow steps",
+            "coarse chain whole, 10 steps per prolongation stage, 5 fine sweeps, 5 flow steps",
+            t1 + t2 + t3 + t4, t1 + t2 * sum(its) / 30 + t3 * 10 + t4 * 20,
+            "prolongation x(156+69+39)/30 steps, sweeps x10, flow x20")
+        tot, tsample = 0.0, 0.0
+        for L in (12, 16, 20):
+            dl = [L] * 4
+            U = oracle.init_hot(dl, 4, 0)
+            t, _ = timed(lambda: oracle.sweep_hb_or(dl, U, 6.0, 4, 0, 0, 2, n_or=4))
+            tsample += t
+            tot += t * 50 * 16
+        rec("C4 16 x (12^4, 16^4, 20^4), 100 sweeps", "2 sweeps of one lattice per size", tsample, tot,
+            "x50 sweeps x16 lattices per size")
+        rate = 5 * 4 * 16 ** 4 * 5 / max(t3, 1e-9)  # link updates/s of the 16^4 sweeps of C3
+        rec("M0 32^4, 1 sweep (1 HB + 4 OR)", "no run: the 16^4 sweep rate of C3", 0.0, 5 * 4 * 32 ** 4 / rate,
+            "by link updates at the 16^4 rate")
+        U = oracle.init_cold(d8)
+        oracle.sweep_hb_or(d8, U, 6.0, 5, 0, 0, 5, n_or=4)
+        t, _ = timed(lambda: oracle.hmc_trajectory(d8, U, 6.0, 1.0, 40, 5, 0, 0, 0))
+        rec("C5 32^4 HMC, 20 trajectories of 40 steps", "one 8^4 trajectory", t, t * 256 * 20, "x256 volume x20")
+    return out
+
+
 def copy_calibration(torch, gib=1.0):
     """A plain device-to-device copy of known size (for scaling HBM counters)."""
     n = int(gib * (1 << 30)) // 4
@@ -351,7 +419,9 @@ def main():
     ap.add_argument("--lattice", type=int, default=32)
     ap.add_argument("--batch", type=int, default=4, help="lattices in the FP32 batched run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of parts to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch,hmc,multiscale,batch48)")
+    ap.add_argument("--only", default="", help="comma list of parts to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch,hmc,multiscale,flow,batch48)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the oracle on bounded samples of each configuration (host only) and exit")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-hmc", action="store_true", help="skip the HMC report")
@@ -365,6 +435,9 @@ def main():
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(independent lattices would shard across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
+    if a.oracle_timing:  # host only: no GPU needed
+        print(json.dumps({"oracle_timing": oracle_timing()}), flush=True)
+        return
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
