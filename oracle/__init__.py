@@ -76,6 +76,8 @@ def lib():
             "orc_wilson_loop": (d, [P, P, i32, i32]),
             "orc_partial_plaquette": (d, [P, P, i32]),
             "orc_displaced_2x2": (d, [P, P, i32]),
+            "orc_displaced_loop": (d, [P, P, i32, i32, i32]),
+            "orc_hb_link": (i64, [P, P, i64, i32, i32, d, u32, u32, u64, i32, i32, i32, P]),
             "orc_wilson_flow": (None, [P, P, d, i32]),
             "orc_topological_charge": (d, [P, P]),
             "orc_clover_energy": (d, [P, P]),
@@ -206,6 +208,21 @@ def hb_pass(dims, U, beta, seed, lattice_id, sweep, n_hits=1, max_tries=64, samp
     return lib().orc_hb_pass(_ptr(_dims(dims)), _ptr(U), beta, seed, lattice_id, sweep, n_hits, max_tries, sampler)
 
 
+def hb_link(dims, U, site, mu, beta, seed, lattice_id, sweep, kind=0, n_hits=1, max_tries=64, sampler=KP,
+            record=False):
+    """Full update of the one link (site, mu) in place, every other link
+    unchanged; kind 0 = heat bath, 1 = overrelaxation.  Returns the number
+    of exhausted draws, and with record=True also an array [n_hits*3, 11]:
+    per (hit, subgroup) step k, outcome (1 applied, 0 exhausted, -1 k = 0),
+    alpha and the applied SU(2) factor r (re, im of r00, r01, r10, r11)."""
+    _chk(U, dims)
+    nh = n_hits if kind == 0 else 1
+    rec = np.zeros((3 * nh, 11)) if record else None
+    ex = lib().orc_hb_link(_ptr(_dims(dims)), _ptr(U), site, mu, kind, beta, seed, lattice_id, sweep, n_hits,
+                           max_tries, sampler, _ptr(rec) if record else None)
+    return (ex, rec) if record else ex
+
+
 def or_pass(dims, U):
     _chk(U, dims)
     lib().orc_or_pass(_ptr(_dims(dims)), _ptr(U))
@@ -308,6 +325,11 @@ def wilson_loop(dims, U, m, n) -> float:
 def partial_plaquette(dims, U, d) -> float:
     _chk(U, dims)
     return lib().orc_partial_plaquette(_ptr(_dims(dims)), _ptr(U), d)
+
+
+def displaced_loop(dims, U, d, m, n) -> float:
+    _chk(U, dims)
+    return lib().orc_displaced_loop(_ptr(_dims(dims)), _ptr(U), d, m, n)
 
 
 def displaced_2x2(dims, U, d) -> float:

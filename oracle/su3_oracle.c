@@ -575,7 +575,7 @@ static void left_apply(mat3* M, int i, int j, cx r[2][2])
  * unchanged.  Returns the number of subgroup draws left unchanged because
  * no trial was accepted. */
 static int update_link(const geom* g, double* U, int64_t i, int mu, int kind, double beta, uint32_t seed,
-                       uint32_t lid, uint64_t sweep, int n_hits, int max_tries, int sampler)
+                       uint32_t lid, uint64_t sweep, int n_hits, int max_tries, int sampler, double* rec)
 {
     mat3 A = staple(g, U, i, mu);
     mat3 u = ld(U, i, mu);
@@ -587,14 +587,18 @@ static int update_link(const geom* g, double* U, int64_t i, int mu, int kind, do
             int a = SUB_I[s], b = SUB_J[s];
             cx v[2][2];
             double k = su2_part(&W, a, b, v);
+            double* rc = rec ? rec + 11 * (3 * h + s) : NULL;
+            if (rc) { memset(rc, 0, 11 * sizeof(double)); rc[0] = k; rc[1] = -1.0; }
             if (k == 0.0) continue;
             cx vd[2][2] = { { conj(v[0][0]), conj(v[1][0]) }, { conj(v[0][1]), conj(v[1][1]) } };
             cx r[2][2];
             if (kind == 0) {
                 double alpha = 2.0 * beta * k / 3.0;
                 double g0;
+                if (rc) rc[2] = alpha;
                 if (!sample_g0(alpha, sampler, max_tries, seed, lid, (uint32_t)i, mu, s, h, sweep, &g0)) {
                     exhausted++;
+                    if (rc) rc[1] = 0.0;
                     continue;
                 }
                 double u[4];
@@ -611,6 +615,14 @@ static int update_link(const geom* g, double* U, int64_t i, int mu, int kind, do
             } else {
                 for (int p = 0; p < 2; p++)
                     for (int q = 0; q < 2; q++) r[p][q] = vd[p][0] * vd[0][q] + vd[p][1] * vd[1][q];
+            }
+            if (rc) {
+                rc[1] = 1.0;
+                for (int p = 0; p < 2; p++)
+                    for (int q = 0; q < 2; q++) {
+                        rc[3 + 2 * (2 * p + q)] = creal(r[p][q]);
+                        rc[4 + 2 * (2 * p + q)] = cimag(r[p][q]);
+                    }
             }
             left_apply(&u, a, b, r);
             left_apply(&W, a, b, r);
@@ -631,7 +643,7 @@ static int64_t pass(const geom* g, double* U, int kind, double beta, uint32_t se
 #pragma omp parallel for reduction(+ : exhausted) schedule(static)
             for (int64_t i = 0; i < g->V; i++) {
                 if (parity_of(g, i) != par) continue;
-                exhausted += update_link(g, U, i, mu, kind, beta, seed, lid, sweep, n_hits, max_tries, sampler);
+                exhausted += update_link(g, U, i, mu, kind, beta, seed, lid, sweep, n_hits, max_tries, sampler, NULL);
             }
         }
     return exhausted;
@@ -642,6 +654,21 @@ int64_t orc_hb_pass(const int32_t L[4], double* U, double beta, uint32_t seed, u
 {
     geom g = mkgeom(L);
     return pass(&g, U, 0, beta, seed, lid, sweep, n_hits, max_tries, sampler);
+}
+
+/* The full update of the single link (site, mu) -- heat bath (kind 0, hits
+ * 0..n_hits-1) or overrelaxation (kind 1) -- with the counters a pass would
+ * use, leaving every other link unchanged (so its staple stays frozen).  If
+ * rec is not NULL it receives 11 doubles per (hit, subgroup) step, in step
+ * order: k, the outcome (1 applied, 0 all trials rejected, -1 skipped with
+ * k = 0), alpha, and the applied 2x2 factor r as (re, im) of r00, r01, r10,
+ * r11 (zero unless applied).  Returns the number of exhausted draws. */
+int64_t orc_hb_link(const int32_t L[4], double* U, int64_t site, int32_t mu, int32_t kind, double beta,
+                    uint32_t seed, uint32_t lid, uint64_t sweep, int32_t n_hits, int32_t max_tries, int32_t sampler,
+                    double* rec)
+{
+    geom g = mkgeom(L);
+    return update_link(&g, U, site, mu, kind, beta, seed, lid, sweep, n_hits, max_tries, sampler, rec);
 }
 
 void orc_or_pass(const int32_t L[4], double* U)
@@ -965,22 +992,29 @@ int32_t orc_prolongate(const int32_t Lc[4], const double* Uc, double* Uf, double
     return 0;
 }
 
-/* Average m x n Wilson loop over all sites and planes mu<nu (Sec. III). */
+/* (1/3) Re Tr of the m x n Wilson loop at site i in the plane (mu, nu):
+ * m steps along +mu, n along +nu, m back along mu, n back along nu (Sec. III,
+ * Wilson loops of the plaquette and of its 2x2 and larger relatives). */
+static double loop_retr(const geom* g, const double* U, int64_t i, int mu, int nu, int m, int n)
+{
+    mat3 P = m_one();
+    int64_t j = i;
+    for (int a = 0; a < m; a++) { P = m_mul(P, ld(U, j, mu)); j = hop(g, j, mu, +1); }
+    for (int b = 0; b < n; b++) { P = m_mul(P, ld(U, j, nu)); j = hop(g, j, nu, +1); }
+    for (int a = 0; a < m; a++) { j = hop(g, j, mu, -1); P = m_mul(P, m_dag(ld(U, j, mu))); }
+    for (int b = 0; b < n; b++) { j = hop(g, j, nu, -1); P = m_mul(P, m_dag(ld(U, j, nu))); }
+    return creal(m_tr(P)) / 3.0;
+}
+
+/* Average m x n Wilson loop over all sites and planes mu<nu (Sec. III);
+ * the m steps go along the lower direction mu of each plane. */
 double orc_wilson_loop(const int32_t L[4], const double* U, int32_t m, int32_t n)
 {
     geom g = mkgeom(L);
     double s = 0;
     for (int64_t i = 0; i < g.V; i++)
         for (int mu = 0; mu < 4; mu++)
-            for (int nu = mu + 1; nu < 4; nu++) {
-                mat3 P = m_one();
-                int64_t j = i;
-                for (int a = 0; a < m; a++) { P = m_mul(P, ld(U, j, mu)); j = hop(&g, j, mu, +1); }
-                for (int b = 0; b < n; b++) { P = m_mul(P, ld(U, j, nu)); j = hop(&g, j, nu, +1); }
-                for (int a = 0; a < m; a++) { j = hop(&g, j, mu, -1); P = m_mul(P, m_dag(ld(U, j, mu))); }
-                for (int b = 0; b < n; b++) { j = hop(&g, j, nu, -1); P = m_mul(P, m_dag(ld(U, j, nu))); }
-                s += creal(m_tr(P)) / 3.0;
-            }
+            for (int nu = mu + 1; nu < 4; nu++) s += loop_retr(&g, U, i, mu, nu, m, n);
     return s / (6.0 * (double)g.V);
 }
 
@@ -1002,29 +1036,29 @@ double orc_partial_plaquette(const int32_t L[4], const double* U, int32_t d)
     return cnt ? s / (double)cnt : NAN;
 }
 
-double orc_displaced_2x2(const int32_t L[4], const double* U, int32_t d)
+/* Displaced m x n loops: the loops of orc_wilson_loop from the sites with
+ * chi(n) = d only (Sec. III, displaced-loop average; its 2x2 case is
+ * W^{2x2}_d, and even-sided loops from chi = 0 sites are the ones the
+ * prolongation preserves). */
+double orc_displaced_loop(const int32_t L[4], const double* U, int32_t d, int32_t m, int32_t n)
 {
     geom g = mkgeom(L);
     double s = 0;
     int64_t cnt = 0;
     for (int64_t i = 0; i < g.V; i++) {
-        int n[4];
-        coords(&g, i, n);
-        if (chi_excl(n, -1, -1) != d) continue;
+        int x[4];
+        coords(&g, i, x);
+        if (chi_excl(x, -1, -1) != d) continue;
         for (int mu = 0; mu < 4; mu++)
             for (int nu = mu + 1; nu < 4; nu++) {
-                mat3 P = m_one();
-                int64_t j = i;
-                for (int a = 0; a < 2; a++) { P = m_mul(P, ld(U, j, mu)); j = hop(&g, j, mu, +1); }
-                for (int b = 0; b < 2; b++) { P = m_mul(P, ld(U, j, nu)); j = hop(&g, j, nu, +1); }
-                for (int a = 0; a < 2; a++) { j = hop(&g, j, mu, -1); P = m_mul(P, m_dag(ld(U, j, mu))); }
-                for (int b = 0; b < 2; b++) { j = hop(&g, j, nu, -1); P = m_mul(P, m_dag(ld(U, j, nu))); }
-                s += creal(m_tr(P)) / 3.0;
+                s += loop_retr(&g, U, i, mu, nu, m, n);
                 cnt++;
             }
     }
     return cnt ? s / (double)cnt : NAN;
 }
+
+double orc_displaced_2x2(const int32_t L[4], const double* U, int32_t d) { return orc_displaced_loop(L, U, d, 2, 2); }
 
 /* ------------------------------------------------------------------ */
 /* Wilson flow (Sec. IV.B), fixed-step third-order Runge-Kutta.         */
