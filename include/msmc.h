@@ -100,9 +100,12 @@ int32_t su3_field_set_stream(su3_field f, void* hip_stream);
 /* dims[4], precision and byte size of a field. */
 int32_t su3_field_info(su3_field f, int32_t dims[4], int32_t* prec, size_t* bytes);
 
-/* Cold start: every link = 1.  Hot start: every link Haar-random from
- * Philox purpose INIT (rows 0,1 complex Gaussians, Gram-Schmidt, row 2 the
- * SU(3) completion), computed in fp64 and rounded to the storage precision. */
+/* The two starts of the thermalization studies (Sec. IV.F: an ordered,
+ * delta-function start and a random one).  Cold start: every link = 1.  Hot
+ * start: every link Haar-random from Philox purpose INIT (rows 0,1 complex
+ * Gaussians, Gram-Schmidt, row 2 the SU(3) completion), computed in fp64 and
+ * rounded to the storage precision.  Errors: SU3_ERR_ARG for a NULL handle,
+ * SU3_ERR_HIP if a launch fails. */
 int32_t su3_init_cold(su3_field f);
 int32_t su3_init_hot(su3_field f, uint32_t seed, uint32_t lattice_id);
 
@@ -139,16 +142,24 @@ int32_t su3_prolongate(su3_field coarse, su3_field fine, double c, double rel_to
  * (Sec. IV.A).  Wilson action at coupling beta.  plaq_hist (n_sweeps
  * doubles, may be NULL) receives the average plaquette after each sweep
  * (after reunitarization when that sweep reunitarizes).  p = NULL uses
- * {4, 1, 64, 0, KP}. */
+ * {n_or 4, n_hb_hits 1, hb_max_tries 64, reunit_every 10, KP}; on fp64
+ * fields, whose links stay in SU(3) to rounding, pass reunit_every = 0 to
+ * follow the paper's schedule exactly.  The count of exhausted draws is
+ * kept per field (su3_last_exhausted). */
 int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattice_id, uint64_t first_sweep,
                         int32_t n_sweeps, const su3_hb_params* p, double* plaq_hist);
 
-/* The same schedule on n independent lattices of equal precision (any
- * shapes) in one batched launch per phase, recorded once into a HIP graph
- * and replayed.  Per lattice: fs[i], betas[i], seeds[i], lattice_ids[i].
- * Results are bitwise equal to n separate su3_sweep_hb_or calls.  plaq_out
- * (n_sweeps * n doubles, [sweep][lattice], may be NULL).  The fields must
- * share one stream. */
+/* Parallel rethermalization of many prolongated lattices (Sec. II, the
+ * strategy in which refined configurations are rethermalized independently,
+ * which the paper notes is embarrassingly parallel): the schedule of
+ * su3_sweep_hb_or on n independent lattices of equal precision (any shapes)
+ * in one batched launch per phase, recorded once into a HIP graph and
+ * replayed.  Per lattice: fs[i], betas[i], seeds[i], lattice_ids[i].
+ * Results are bitwise equal to n separate su3_sweep_hb_or calls, the
+ * exhausted-draw count of each field included.  plaq_out (n_sweeps * n
+ * doubles, [sweep][lattice], may be NULL).  The fields must share one
+ * stream and appear once each (SU3_ERR_ARG), and share one precision
+ * (SU3_ERR_UNSUPPORTED). */
 int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* betas, const uint32_t* seeds,
                               const uint32_t* lattice_ids, uint64_t first_sweep, int32_t n_sweeps,
                               const su3_hb_params* p, double* plaq_out);
@@ -165,9 +176,12 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
 int32_t su3_hmc_trajectory(su3_field f, double beta, double tau, int32_t n_steps, uint32_t seed,
                            uint32_t lattice_id, uint64_t traj, int32_t metropolis, double* dH, int32_t* accepted);
 
-/* Average plaquette (1/(6V)) sum_n sum_{mu<nu} (1/3) Re Tr U_munu(n), fp64. */
+/* Sec. III, the Wilson action and the 1 x 1 Wilson loops W_munu(n):
+ * su3_plaquette gives the average plaquette
+ * (1/(6V)) sum_n sum_{mu<nu} (1/3) Re Tr U_munu(n), su3_action the Wilson
+ * action beta sum_n sum_{mu<nu} [1 - (1/3) Re Tr U_munu(n)].  Both are
+ * summed in fp64 in a fixed order (the same bits for any launch shape). */
 int32_t su3_plaquette(su3_field f, double* out);
-/* Wilson action beta sum_n sum_{mu<nu} [1 - (1/3) Re Tr U_munu(n)], fp64. */
 int32_t su3_action(su3_field f, double beta, double* out);
 
 /* n_steps fixed steps eps of the third-order Runge-Kutta Wilson flow, in
@@ -201,11 +215,17 @@ int32_t su3_flow_t0(const double* t, const double* E, int32_t n, double target, 
  * topological sectors. */
 int32_t su3_max_plaquette_action(su3_field f, double* h);
 
-/* Clover topological charge: F_munu = traceless part of (Q_munu -
- * Q_munu^+)/8 with Q_munu the four-leaf clover, q(x) = -(1/(2 pi^2))
- * Re Tr[F01 F23 - F02 F13 + F03 F12], Q = sum_x q(x); fp64. */
+/* Topological charge of the current field (Sec. IV.D).  The paper measures
+ * it with a three-loop improved gluonic operator whose coefficients it does
+ * not give; this library uses the clover definition: F_munu = traceless
+ * part of (Q_munu - Q_munu^+)/8 with Q_munu the four-leaf clover,
+ * q(x) = -(1/(2 pi^2)) Re Tr[F01 F23 - F02 F13 + F03 F12] (epsilon_0123 =
+ * +1), Q = sum_x q(x), in fp64.  Like it, Q approaches integers along the
+ * Wilson flow. */
 int32_t su3_topological_charge(su3_field f, double* Q);
-/* Clover energy density (1/V) sum_x sum_{mu<nu} -Re Tr(F_munu F_munu). */
+/* Clover energy density (Sec. IV.B, the E(t) that defines the flow scale
+ * t0): (1/V) sum_x sum_{mu<nu} -Re Tr(F_munu F_munu) with the F_munu of
+ * su3_topological_charge, fp64. */
 int32_t su3_clover_energy(su3_field f, double* E);
 
 /* Wilson loops (Sec. III, the m x n loop, its plane/site average and the
@@ -225,11 +245,15 @@ int32_t su3_wilson_loop(su3_field f, int32_t m, int32_t n, double* out);
 int32_t su3_partial_plaquettes(su3_field f, double out[3]);
 int32_t su3_displaced_loops(su3_field f, double out[5]);
 
-/* Reunitarize every link (Gram-Schmidt of rows 0,1 in fp64). */
+/* Reunitarize every link (Gram-Schmidt of rows 0,1 in fp64).  Not a step of
+ * the paper, whose precision is unstated: it returns reduced-precision links
+ * to SU(3) (the sweeps do it every reunit_every sweeps). */
 int32_t su3_reunitarize(su3_field f);
 
 /* Random gauge transformation U_mu(n) -> Om(n) U_mu(n) Om(n+mu)^+ with Om
- * Haar-random per site from Philox purpose GAUGE, key (seed, 0). */
+ * Haar-random per site from Philox purpose GAUGE, key (seed, 0): the gauge
+ * freedom of the action (Sec. III), used to check that measurements are
+ * gauge invariant. */
 int32_t su3_gauge_transform(su3_field f, uint32_t seed);
 
 /* Largest deviation of any link from SU(3) (the largest entry modulus of
@@ -238,8 +262,10 @@ int32_t su3_gauge_transform(su3_field f, uint32_t seed);
  * SU3_ERR_NUMERIC when the deviation exceeds tol (outputs still written). */
 int32_t su3_check_field(su3_field f, double tol, double* max_dev, int64_t* worst);
 
-/* Heat-bath draws left unchanged because every trial was rejected, summed
- * over the last su3_sweep_hb_or / su3_batch_sweep_hb_or call on f. */
+/* Heat-bath draws left unchanged because every trial was rejected (the
+ * paper's cap on attempted updates, Sec. IV.A), summed over the last
+ * su3_sweep_hb_or or su3_batch_sweep_hb_or call that swept f: after a batch
+ * each field holds its own lattice's count. */
 int32_t su3_last_exhausted(su3_field f, int64_t* count);
 
 /* Launch shape of the checkerboard phase kernels: block in {64, 128, 256,

@@ -110,7 +110,7 @@ def _dims(dims):
     return a
 
 
-def hb_params(n_or=4, n_hb_hits=1, hb_max_tries=64, reunit_every=0, sampler=SU3_SAMPLER_KP) -> HbParams:
+def hb_params(n_or=4, n_hb_hits=1, hb_max_tries=64, reunit_every=10, sampler=SU3_SAMPLER_KP) -> HbParams:
     return HbParams(n_or, n_hb_hits, hb_max_tries, reunit_every, sampler)
 
 

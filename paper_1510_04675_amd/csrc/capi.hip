@@ -69,6 +69,11 @@ __global__ void k_set_u64(uint64_t* p, uint64_t v)
     if (threadIdx.x == 0) *p = v;
 }
 
+__global__ void k_zero_u64(unsigned long long* p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
 static hipError_t upload_descs(LatDesc* dst, const std::vector<LatDesc>& src, hipStream_t st)
 {
     for (size_t o = 0; o < src.size(); o += kDescChunk) {
@@ -162,7 +167,7 @@ struct Plan {
     double* d_out = nullptr;  // reduction results
     int out_cap = 0;
     uint64_t* d_sweep = nullptr;
-    unsigned long long* d_exh = nullptr;
+    unsigned long long* d_exh = nullptr;  // exhausted heat-bath draws, one counter per lattice
     std::vector<LatDesc> host_descs;
     std::vector<int> bbeg_phase_h, bbeg_link_h, bbeg_site_h, bbeg_lw_h;
 
@@ -357,7 +362,7 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
         // up to 5 classes of site partials (Wilson loop classes) or one per link block
         HIPCHK(hipMalloc(&p.d_partials, sizeof(double) * std::max({ 5 * p.nblk_site, p.nblk_link, p.nblk_lw })));
         HIPCHK(hipMalloc(&p.d_sweep, sizeof(uint64_t)));
-        HIPCHK(hipMalloc(&p.d_exh, sizeof(unsigned long long)));
+        HIPCHK(hipMalloc(&p.d_exh, sizeof(unsigned long long) * p.nlat));
     }
     if (out_cap > p.out_cap) {
         hipFree(p.d_out);
@@ -499,14 +504,15 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
         // next group starts, so its links stay cached between phases.
         for (int grp = 0; grp < ng; grp++) {
             const Grid gph = ng > 1 ? p.grid_phase_group(grp) : p.grid_phase();
+            unsigned long long* exh = p.d_exh + (ng > 1 ? p.grp_first[grp] : 0);
             ProfMark pm{ prof_marks, st };
             for (int pass = 0; pass <= o.n_or; pass++) {
                 const int kind = pass == 0 ? 0 : 1;
                 if (pass <= 1 && (rc = pm.begin())) return rc;
                 for (int mu = 0; mu < 4; mu++)
                     for (int par = 0; par < 2; par++)
-                        HIPCHK(launch_phase(p.prec, kind, gph, mu, par, p.d_sweep, k, hb,
-                                            kind == 0 ? p.d_exh : nullptr, st));
+                        HIPCHK(launch_phase(p.prec, kind, gph, mu, par, p.d_sweep, k, hb, kind == 0 ? exh : nullptr,
+                                            st));
                 if (pass == 0 && (rc = pm.end(0, 8))) return rc;
                 if (pass == o.n_or && pass > 0 && (rc = pm.end(1, 8 * o.n_or))) return rc;
             }
@@ -525,7 +531,7 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
 
 static int32_t validate_hb(const su3_hb_params* pp, SweepOpts& o)
 {
-    su3_hb_params d{ 4, 1, 64, 0, SU3_SAMPLER_KP };
+    su3_hb_params d{ 4, 1, 64, 10, SU3_SAMPLER_KP };
     const su3_hb_params& p = pp ? *pp : d;
     if (p.n_or < 0 || p.n_or > 1000) return fail(SU3_ERR_ARG, "n_or must be in [0, 1000]");
     if (p.n_hb_hits < 1 || p.n_hb_hits > 255) return fail(SU3_ERR_ARG, "n_hb_hits must be in [1, 255]");
@@ -944,7 +950,7 @@ int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattic
     d[0].lid = lattice_id;
     HIPCHK(upload_descs(p.d_descs, d, f->stream));
     k_set_u64<<<1, 1, 0, f->stream>>>(p.d_sweep, first_sweep);
-    k_set_u64<<<1, 1, 0, f->stream>>>((uint64_t*)p.d_exh, 0);
+    k_zero_u64<<<1, 64, 0, f->stream>>>(p.d_exh, 1);
     HIPCHK(hipGetLastError());
     std::vector<ProfRun> marks;
     const bool prof = g_profile;
@@ -1067,7 +1073,7 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
     }
     HIPCHK(upload_descs(p.d_descs, p.host_descs, st));
     k_set_u64<<<1, 1, 0, st>>>(p.d_sweep, first_sweep);
-    k_set_u64<<<1, 1, 0, st>>>((uint64_t*)p.d_exh, 0);
+    k_zero_u64<<<1, 256, 0, st>>>(p.d_exh, n);
     HIPCHK(hipGetLastError());
     std::vector<ProfRun> marks;
     if (prof) {
@@ -1075,16 +1081,15 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
     } else {
         HIPCHK(hipGraphLaunch(ge->exec, st));
     }
-    unsigned long long ex = 0;
-    HIPCHK(hipMemcpyAsync(&ex, p.d_exh, sizeof ex, hipMemcpyDeviceToHost, st));
+    std::vector<unsigned long long> ex(n, 0ull);
+    HIPCHK(hipMemcpyAsync(ex.data(), p.d_exh, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, st));
     std::vector<double> h;
     if (o.record) {
         h.resize((size_t)n_sweeps * n);
         HIPCHK(hipMemcpyAsync(h.data(), p.d_out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
-    for (auto* f : v) f->last_exhausted = 0;
-    v[0]->last_exhausted = (int64_t)ex;
+    for (int i = 0; i < n; i++) v[i]->last_exhausted = (int64_t)ex[i];
     if (o.record)
         for (int k = 0; k < n_sweeps; k++)
             for (int i = 0; i < n; i++) plaq_out[(size_t)k * n + i] = 1.0 - h[(size_t)k * n + i] / (6.0 * v[i]->V);

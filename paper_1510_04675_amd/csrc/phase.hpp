@@ -15,6 +15,8 @@
 //
 // One thread per link of direction mu and the given parity; no two links of
 // one phase share a plaquette, so the phase is a single data-parallel launch.
+// exhausted (may be NULL) holds one counter per lattice of the launch, indexed
+// like its descriptors.
 #pragma once
 
 #include <type_traits>
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
                     const double alpha = 2.0 * beta * k / 3.0;
                     double g0;
                     if (!draw_g0<double>(rng, alpha, mu, sg, h, hb, g0)) {
-                        if (exhausted) atomicAdd(exhausted, 1ull);
+                        if (exhausted) atomicAdd(exhausted + l, 1ull);
                         continue;
                     }
                     double q[4];
@@ -154,7 +156,7 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
                     const R alpha = R(2) * beta * k / R(3);
                     R g0;
                     if (!draw_g0<R>(rng, alpha, mu, sg, h, hb, g0)) {
-                        if (exhausted) atomicAdd(exhausted, 1ull);
+                        if (exhausted) atomicAdd(exhausted + l, 1ull);
                         continue;
                     }
                     R q[4];

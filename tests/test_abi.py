@@ -75,3 +75,37 @@ def test_host_only_entry_points_validate_and_compute():
     assert L.su3_set_launch(0, 2) == 1
     assert L.su3_set_launch(0, 1) == 0
     assert L.su3_set_group_bytes(224 << 20) == 0
+
+
+# Entry points that implement a step or a measurement of the method; each
+# must name the passage of the paper it follows in the comment above its
+# declaration.  (Field plumbing, launch tuning and diagnostics have none.)
+METHOD_CALLS = ["su3_init_cold", "su3_init_hot", "su3_restrict", "su3_prolongate", "su3_sweep_hb_or",
+                "su3_batch_sweep_hb_or", "su3_hmc_trajectory", "su3_plaquette", "su3_action", "su3_wilson_flow",
+                "su3_wilson_flow_adaptive", "su3_flow_t0", "su3_max_plaquette_action", "su3_topological_charge",
+                "su3_clover_energy", "su3_wilson_loop", "su3_partial_plaquettes", "su3_displaced_loops",
+                "su3_gauge_transform", "su3_last_exhausted"]
+
+
+def _comment_before(txt, name):
+    """The comment block that documents `name`: the last /* ... */ ending
+    before its declaration (declarations of a group share one comment)."""
+    i = re.search(r"\bint32_t\s+" + name + r"\s*\(", txt).start()
+    j = txt.rfind("*/", 0, i)
+    k = txt.rfind("/*", 0, j)
+    return txt[k:j]
+
+
+def test_method_entry_points_cite_the_paper():
+    txt = open(HEADER).read()
+    for n in METHOD_CALLS:
+        c = _comment_before(txt, n)
+        assert re.search(r"Sec\. [IV]+|App\. [A-D]", c), n
+
+
+def test_last_exhausted_validates():
+    from paper_1510_04675_amd import capi
+    L = capi.lib()
+    c = C.c_int64(7)
+    assert L.su3_last_exhausted(None, C.byref(c)) == 1
+    assert c.value == 7

@@ -172,6 +172,31 @@ def test_sampler_hits_and_exhaustion_match_oracle(m, orc, sampler, hits, tries):
     assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
 
 
+@pytest.mark.parametrize("gbytes", [224 << 20, 1])
+def test_batch_exhaustion_counts_per_lattice(m, orc, gbytes):
+    """With one heat-bath trial per draw at beta = 1 many draws are left
+    unchanged; after a batched call each field reports its own lattice's
+    count (equal to the oracle's for that lattice alone), whether the batch
+    runs as one lattice group or one group per lattice."""
+    shapes = [[4, 4, 4, 4], [4, 2, 4, 2], [6, 4, 2, 4]]
+    betas = [1.0, 0.8, 1.2]
+    m.su3_set_group_bytes(gbytes)
+    try:
+        fs = [field(m, d) for d in shapes]
+        for i, f in enumerate(fs):
+            m.su3_init_hot(f, 30 + i, i)
+        m.su3_batch_sweep_hb_or(fs, betas, [30, 31, 32], [0, 1, 2], 5, 2, P(n_or=1, tries=1))
+        counts = [m.su3_last_exhausted(f) for f in fs]
+    finally:
+        m.su3_set_group_bytes(224 << 20)
+    for i, d in enumerate(shapes):
+        U = orc.init_hot(d, 30 + i, i)
+        _, ex = orc.sweep_hb_or(d, U, betas[i], 30 + i, i, 5, 2, n_or=1, hb_max_tries=1)
+        assert ex > 0
+        assert counts[i] == ex, (i, counts, ex)
+        assert np.max(np.abs(m.su3_field_to_host(fs[i]) - U)) < 1e-12
+
+
 def fp32_link_stats(Ugpu, Uref):
     """Per-link largest component deviation: median, 99.9th percentile, max."""
     dev = np.max(np.abs(Ugpu - Uref), axis=(2, 3, 4)).ravel()
