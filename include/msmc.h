@@ -149,6 +149,24 @@ int32_t su3_prolongate(su3_field coarse, su3_field fine, double c, double rel_to
 int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattice_id, uint64_t first_sweep,
                         int32_t n_sweeps, const su3_hb_params* p, double* plaq_hist);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sweeps
+ * of su3_sweep_hb_or, same arguments, same kernels and bitwise the same
+ * results, with no allocation of any kind.  The tables, counters, plaquette
+ * partials and history it needs live in a fixed device array of 557,824
+ * bytes that each GPU the library runs on holds until the process ends;
+ * the field itself is the caller's (su3_field_wrap allocates nothing).
+ * Limits: at most 2^24 sites (SU3_ERR_UNSUPPORTED beyond) and at most 4096
+ * sweeps per call when plaq_hist is given (SU3_ERR_ARG beyond).  It uses the
+ * default launch shape or the one forced by su3_set_launch / su3_set_tile,
+ * never runs the autotuner and is not timed by su3_profile_enable.  Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (other threads, other streams) race and must be serialized by the
+ * caller.  Like su3_sweep_hb_or it synchronizes the field's stream before
+ * returning. */
+int32_t su3_sweep_hb_or_noalloc(su3_field f, double beta, uint32_t seed, uint32_t lattice_id, uint64_t first_sweep,
+                                int32_t n_sweeps, const su3_hb_params* p, double* plaq_hist);
+
 /* Parallel rethermalization of many prolongated lattices (Sec. II, the
  * strategy in which refined configurations are rethermalized independently,
  * which the paper notes is embarrassingly parallel): the schedule of

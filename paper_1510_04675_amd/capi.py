@@ -47,6 +47,7 @@ SIGNATURES = {
     "su3_restrict": (_i32, [_p, _p]),
     "su3_prolongate": (_i32, [_p, _p, _d, _d, _i32, _p]),
     "su3_sweep_hb_or": (_i32, [_p, _d, _u32, _u32, _u64, _i32, C.POINTER(HbParams), _p]),
+    "su3_sweep_hb_or_noalloc": (_i32, [_p, _d, _u32, _u32, _u64, _i32, C.POINTER(HbParams), _p]),
     "su3_batch_sweep_hb_or": (_i32, [_p, _i32, _p, _p, _p, _u64, _i32, C.POINTER(HbParams), _p]),
     "su3_hmc_trajectory": (_i32, [_p, _d, _d, _i32, _u32, _u32, _u64, _i32, C.POINTER(_d), C.POINTER(_i32)]),
     "su3_plaquette": (_i32, [_p, C.POINTER(_d)]),
@@ -216,6 +217,15 @@ def su3_sweep_hb_or(f: Field, beta, seed, lattice_id=0, first_sweep=0, n_sweeps=
     pp = C.byref(params) if params is not None else None
     _ck(lib().su3_sweep_hb_or(f.handle, beta, seed, lattice_id, first_sweep, n_sweeps, pp,
                               hist.ctypes.data_as(C.c_void_p) if record else None))
+    return hist[:n_sweeps] if record else None
+
+
+def su3_sweep_hb_or_noalloc(f: Field, beta, seed, lattice_id=0, first_sweep=0, n_sweeps=1, params: HbParams = None,
+                            record=True):
+    hist = np.zeros(max(n_sweeps, 1))
+    pp = C.byref(params) if params is not None else None
+    _ck(lib().su3_sweep_hb_or_noalloc(f.handle, beta, seed, lattice_id, first_sweep, n_sweeps, pp,
+                                      hist.ctypes.data_as(C.c_void_p) if record else None))
     return hist[:n_sweeps] if record else None
 
 

@@ -497,7 +497,8 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
                               std::vector<ProfRun>* prof_marks)
 {
     const HbArgs hb{ o.n_hits, o.max_tries, o.sampler };
-    const int ng = p.ngroups();
+    // a plan without group tables sweeps all its lattices as one group
+    const int ng = std::max(1, p.ngroups());
     int32_t rc;
     for (int k = 0; k < n_sweeps; k++) {
         // Lattices are independent: each group runs its whole sweep before the
@@ -751,6 +752,66 @@ static int32_t action_density_sum(su3_field_s* f, const LatDesc* d, double* out)
 }
 
 // ---------------------------------------------------------------------------
+// Allocation-free sweeps: the tables, counters, plaquette partials and
+// history of one lattice live in a fixed device array instead of per-field
+// allocations.  Layout (bytes): descriptor [0, 256), block tables
+// [256, 512), sweep index and exhausted-draw counter [512, 768), plaquette
+// block partials (one double per 256 sites) [768, 768 + 8 * kNaPartials),
+// then the per-sweep sums (kNaMaxRecord doubles).
+// ---------------------------------------------------------------------------
+constexpr long long kNaMaxSites = 1LL << 24;  // e.g. 64^4
+constexpr int kNaMaxRecord = 4096;            // sweeps with a plaquette history per call
+constexpr size_t kNaPartials = (size_t)(kNaMaxSites / 256);
+constexpr size_t kNaOffDesc = 0, kNaOffInts = 256, kNaOffCounters = 512, kNaOffPartials = 768;
+constexpr size_t kNaOffOut = kNaOffPartials + sizeof(double) * kNaPartials;
+constexpr size_t kNaBytes = kNaOffOut + sizeof(double) * kNaMaxRecord;
+static_assert(sizeof(LatDesc) <= kNaOffInts - kNaOffDesc, "descriptor slot too small");
+
+// Each GPU the library runs on holds one copy until the process ends.
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+static std::mutex g_na_mu;
+constexpr int kNaMaxDevices = 64;
+static void* g_na_ptr[kNaMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device (the array's name is not a device address in host code).
+static int32_t na_scratch(unsigned char** out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(SU3_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SU3_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_na_ptr[dev] = ptr;
+    }
+    *out = (unsigned char*)g_na_ptr[dev];
+    return SU3_OK;
+}
+
+// Launch shape of the allocation-free sweeps: the default, or the shape
+// forced by su3_set_launch / su3_set_tile (autotuned shapes are not used).
+static LaunchCfg na_launch_cfg()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    LaunchCfg c = default_cfg();
+    if (g_forced_block > 0) {
+        c.block = g_forced_block;
+        c.remap = g_forced_remap;
+    }
+    if (g_tile_forced) {
+        c.ty = g_forced_tile[0];
+        c.tz = g_forced_tile[1];
+        c.tt = g_forced_tile[2];
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -966,6 +1027,84 @@ int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattic
     f->last_exhausted = (int64_t)ex;
     for (int k = 0; k < (int)h.size(); k++) plaq_hist[k] = 1.0 - h[k] / (6.0 * f->V);
     if (prof && (rc = read_marks(marks))) return rc;
+    return SU3_OK;
+}
+
+int32_t su3_sweep_hb_or_noalloc(su3_field f, double beta, uint32_t seed, uint32_t lattice_id, uint64_t first_sweep,
+                                int32_t n_sweeps, const su3_hb_params* pp, double* plaq_hist)
+{
+    int32_t rc = check_field(f);
+    if (rc) return rc;
+    SweepOpts o;
+    if ((rc = validate_hb(pp, o))) return rc;
+    if (n_sweeps < 0) return fail(SU3_ERR_ARG, "n_sweeps must be >= 0");
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(SU3_ERR_ARG, "beta must be finite and >= 0");
+    if ((long long)f->V > kNaMaxSites)
+        return fail(SU3_ERR_UNSUPPORTED, "su3_sweep_hb_or_noalloc takes at most 2^24 sites (this field has " +
+                                             std::to_string(f->V) + ")");
+    o.record = plaq_hist != nullptr;
+    if (o.record && n_sweeps > kNaMaxRecord)
+        return fail(SU3_ERR_ARG, "su3_sweep_hb_or_noalloc records at most 4096 sweeps per call");
+    unsigned char* base = nullptr;
+    if ((rc = na_scratch(&base))) return rc;
+    hipStream_t st = f->stream;
+
+    // tables of one lattice, written by kernels into the scratch array
+    const LaunchCfg cfg = na_launch_cfg();
+    LatDesc d = base_desc(f);
+    d.tile[0] = largest_divisor_upto(f->L[1], cfg.ty);
+    d.tile[1] = largest_divisor_upto(f->L[2], cfg.tz);
+    d.tile[2] = largest_divisor_upto(f->L[3], cfg.tt);
+    d.beta = beta;
+    d.seed = seed;
+    d.lid = lattice_id;
+    Plan p;  // views into the scratch array; it owns nothing and is never released
+    p.nlat = 1;
+    p.prec = f->prec;
+    p.cfg = cfg;
+    p.phase_block = cfg.block;
+    p.remap = cfg.remap;
+    p.nblk_phase = ceil_div(f->Vh, cfg.block);
+    p.nblk_link = ceil_div(8LL * f->Vh, 256);
+    p.nblk_site = ceil_div(2LL * f->Vh, 256);
+    p.nblk_lw = 2 * ceil_div(f->Vh, 64);
+    p.d_descs = (LatDesc*)(base + kNaOffDesc);
+    int* ints = (int*)(base + kNaOffInts);
+    p.d_bbeg_phase = ints;
+    p.d_bbeg_link = ints + 2;
+    p.d_bbeg_site = ints + 4;
+    p.d_bbeg_lw = ints + 6;
+    p.d_sweep = (uint64_t*)(base + kNaOffCounters);
+    p.d_exh = (unsigned long long*)(base + kNaOffCounters + 8);
+    p.d_partials = (double*)(base + kNaOffPartials);
+    p.d_out = (double*)(base + kNaOffOut);
+    p.out_cap = kNaMaxRecord;
+    {
+        DescPack dp;
+        memset(&dp, 0, sizeof dp);
+        dp.n = 1;
+        dp.d[0] = d;
+        k_fill_descs<<<1, 64, 0, st>>>(dp, p.d_descs);
+        IntPack ip;
+        memset(&ip, 0, sizeof ip);
+        ip.n = 8;
+        const int v[8] = { 0, p.nblk_phase, 0, p.nblk_link, 0, p.nblk_site, 0, p.nblk_lw };
+        for (int k = 0; k < 8; k++) ip.v[k] = v[k];
+        k_fill_ints<<<1, 64, 0, st>>>(ip, ints);
+    }
+    // the array keeps the previous call's contents: reset what starts at zero
+    k_set_u64<<<1, 1, 0, st>>>(p.d_sweep, first_sweep);
+    k_zero_u64<<<1, 64, 0, st>>>(p.d_exh, 1);
+    HIPCHK(hipGetLastError());
+    if ((rc = enqueue_sweeps(p, n_sweeps, o, st, nullptr))) return rc;
+    unsigned long long ex = 0;
+    HIPCHK(hipMemcpyAsync(&ex, p.d_exh, sizeof ex, hipMemcpyDeviceToHost, st));
+    if (o.record && n_sweeps > 0)
+        HIPCHK(hipMemcpyAsync(plaq_hist, p.d_out, sizeof(double) * n_sweeps, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    f->last_exhausted = (int64_t)ex;
+    if (o.record)
+        for (int k = 0; k < n_sweeps; k++) plaq_hist[k] = 1.0 - plaq_hist[k] / (6.0 * f->V);
     return SU3_OK;
 }
 

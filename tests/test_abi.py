@@ -109,3 +109,21 @@ def test_last_exhausted_validates():
     c = C.c_int64(7)
     assert L.su3_last_exhausted(None, C.byref(c)) == 1
     assert c.value == 7
+
+
+def test_noalloc_sweep_validates_sizes_before_device_work():
+    """The allocation-free sweep rejects a lattice beyond its 2^24-site
+    scratch before any device call (the wrapped pointer is never touched)."""
+    from paper_1510_04675_amd import capi
+    L = capi.lib()
+    dims = (C.c_int32 * 4)(64, 64, 64, 128)
+    nbytes = capi.su3_field_bytes(list(dims), capi.SU3_FP32_R12)
+    h = C.c_void_p()
+    assert L.su3_field_wrap(dims, capi.SU3_FP32_R12, C.c_void_p(1 << 20), nbytes, None, C.byref(h)) == 0
+    try:
+        assert L.su3_sweep_hb_or_noalloc(h, C.c_double(6.0), 1, 0, 0, 1, None, None) == 6
+        assert "2^24" in capi.su3_last_error()
+        assert L.su3_sweep_hb_or_noalloc(h, C.c_double(-1.0), 1, 0, 0, 1, None, None) == 1
+        assert L.su3_sweep_hb_or_noalloc(None, C.c_double(6.0), 1, 0, 0, 1, None, None) == 1
+    finally:
+        L.su3_field_destroy(h)
