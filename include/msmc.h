@@ -151,8 +151,11 @@ int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattic
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the sweeps
- * of su3_sweep_hb_or, same arguments, same kernels and bitwise the same
- * results, with no allocation of any kind.  The tables, counters, plaquette
+ * of su3_sweep_hb_or, same arguments and update kernels, bitwise the same
+ * links and exhausted-draw counts, with no allocation of any kind.  Its
+ * plaquette history comes from the standalone plaquette kernel rather than
+ * from the last overrelaxation pass, so it agrees with su3_sweep_hb_or's to
+ * rounding (1e-13 in fp64, 1e-7 in fp32).  The tables, counters, plaquette
  * partials and history it needs live in a fixed device array of 557,824
  * bytes that each GPU the library runs on holds until the process ends;
  * the field itself is the caller's (su3_field_wrap allocates nothing).
@@ -291,7 +294,7 @@ int32_t su3_last_exhausted(su3_field f, int64_t* count);
  * Results do not depend on it.  su3_autotune(1) makes the next sweep call
  * time the candidates (3 blocks x 2 remaps x 7 tiles) on cold-start scratch
  * fields of the same shapes, swept at that call's couplings and options, and
- * keep the fastest for those shapes; the default (256, remap, tile 16 x 8 x 4) is kept unless
+ * keep the fastest for those shapes; the default (256, remap, tile 8 x 8 x 8) is kept unless
  * another shape is faster by more than 1.5 %.  The scratch fields are
  * allocated and freed inside that call. */
 int32_t su3_set_launch(int32_t block, int32_t xcd_remap);
@@ -308,7 +311,7 @@ int32_t su3_set_group_bytes(uint64_t bytes);
 /* Site tile of the checkerboard phase kernels: threads walk each lattice in
  * tiles of L0 x ty x tz x tt sites (each extent clamped to the largest
  * divisor of L1, L2, L3 not above it; 0 = whole extent).  (0, 0, 0) restores
- * the automatic choice (autotuned, else 16 x 8 x 4).  Results do not depend
+ * the automatic choice (autotuned, else 8 x 8 x 8).  Results do not depend
  * on it; it sets which neighbour links are loaded together into one L2. */
 int32_t su3_set_tile(int32_t ty, int32_t tz, int32_t tt);
 

@@ -165,6 +165,13 @@ struct Plan {
     int* d_bbeg_grp = nullptr;
     double* d_partials = nullptr;
     double* d_out = nullptr;  // reduction results
+    // plaquette site values written by the last overrelaxation pass of a
+    // sweep (3 Vh doubles per lattice), their block tables and partials
+    double* d_psite = nullptr;
+    size_t psite_cap = 0;
+    int* d_bbeg_psite = nullptr;
+    double* d_partials2 = nullptr;
+    int nblk_psite = 0;
     int out_cap = 0;
     uint64_t* d_sweep = nullptr;
     unsigned long long* d_exh = nullptr;  // exhausted heat-bath draws, one counter per lattice
@@ -183,6 +190,13 @@ struct Plan {
         hipFree(d_out);
         hipFree(d_sweep);
         hipFree(d_exh);
+        hipFree(d_psite);
+        hipFree(d_bbeg_psite);
+        hipFree(d_partials2);
+        d_psite = d_partials2 = nullptr;
+        d_bbeg_psite = nullptr;
+        psite_cap = 0;
+        nblk_psite = 0;
         d_descs = nullptr;
         d_bbeg_phase = d_bbeg_link = d_bbeg_site = d_bbeg_lw = d_bbeg_grp = nullptr;
         grp_first.clear();
@@ -213,6 +227,8 @@ struct Plan {
     {
         return Grid{ descs ? descs : d_descs, d_bbeg_lw, nlat, nblk_lw, 256, 1 };
     }
+    // plaquette site values, 1024 per block
+    Grid grid_psite() const { return Grid{ d_descs, d_bbeg_psite, nlat, nblk_psite, 256, 0 }; }
 };
 
 struct su3_field_s {
@@ -299,8 +315,10 @@ static int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 // 0: the whole batch is one group.
 static size_t g_group_bytes = (size_t)224 << 20;
 
+// With psite the plan also holds the buffers that let the sweeps form the
+// plaquette in their last overrelaxation pass.
 static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const LaunchCfg& cfg, int out_cap,
-                          hipStream_t st)
+                          hipStream_t st, bool psite = false)
 {
     const bool shape_change = p.nlat != (int)fs.size();
     if (shape_change) p.release();
@@ -325,6 +343,12 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
         p.bbeg_link_h.push_back(p.bbeg_link_h.back() + ceil_div(8LL * f->Vh, 256));
         p.bbeg_site_h.push_back(p.bbeg_site_h.back() + ceil_div(2LL * f->Vh, 256));
         p.bbeg_lw_h.push_back(p.bbeg_lw_h.back() + 2 * ceil_div(f->Vh, 64));
+    }
+    std::vector<int> bbeg_psite_h(1, 0);
+    size_t psite_n = 0;
+    for (auto* f : fs) {
+        bbeg_psite_h.push_back(bbeg_psite_h.back() + ceil_div(3LL * f->Vh, 1024));
+        psite_n += 3 * (size_t)f->Vh;
     }
     p.nblk_phase = p.bbeg_phase_h.back();
     p.nblk_link = p.bbeg_link_h.back();
@@ -370,6 +394,27 @@ static int32_t plan_build(Plan& p, const std::vector<su3_field_s*>& fs, const La
         HIPCHK(hipMalloc(&p.d_out, sizeof(double) * out_cap));
         p.out_cap = out_cap;
     }
+    if (psite && p.psite_cap < psite_n) {
+        hipFree(p.d_psite);
+        hipFree(p.d_bbeg_psite);
+        hipFree(p.d_partials2);
+        p.d_psite = p.d_partials2 = nullptr;
+        p.d_bbeg_psite = nullptr;
+        p.psite_cap = 0;
+        HIPCHK(hipMalloc(&p.d_psite, sizeof(double) * psite_n));
+        HIPCHK(hipMalloc(&p.d_bbeg_psite, sizeof(int) * (p.nlat + 1)));
+        HIPCHK(hipMalloc(&p.d_partials2, sizeof(double) * bbeg_psite_h.back()));
+        p.psite_cap = psite_n;
+    }
+    if (p.d_psite) {
+        p.nblk_psite = bbeg_psite_h.back();
+        size_t off = 0;
+        for (int i = 0; i < p.nlat; i++) {
+            p.host_descs[i].psite = p.d_psite + off;
+            off += 3 * (size_t)fs[i]->Vh;
+        }
+        HIPCHK(upload_ints(p.d_bbeg_psite, bbeg_psite_h, st));
+    }
     HIPCHK(upload_descs(p.d_descs, p.host_descs, st));
     HIPCHK(upload_ints(p.d_bbeg_phase, p.bbeg_phase_h, st));
     HIPCHK(upload_ints(p.d_bbeg_link, p.bbeg_link_h, st));
@@ -402,15 +447,17 @@ static std::string shape_key(const std::vector<su3_field_s*>& fs)
     return k;
 }
 
-// Default tile: 16 x 8 x 4 sites in (y, z, t) when the extents allow it.
+// Default tile: 8 x 8 x 8 sites in (y, z, t) when the extents allow it (with
+// XCD-contiguous block ranges each XCD then sweeps a compact region; at 32^4 a
+// 12-real overrelaxation phase fetched 2 % less than with 16 x 8 x 4).
 static LaunchCfg default_cfg()
 {
     LaunchCfg c;
     c.block = 256;
     c.remap = 1;
-    c.ty = 16;
+    c.ty = 8;
     c.tz = 8;
-    c.tt = 4;
+    c.tt = 8;
     return c;
 }
 
@@ -499,6 +546,9 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
     const HbArgs hb{ o.n_hits, o.max_tries, o.sampler };
     // a plan without group tables sweeps all its lattices as one group
     const int ng = std::max(1, p.ngroups());
+    // the plaquette is formed in the last overrelaxation pass when the plan
+    // has the buffers for it
+    const bool fused = o.record && p.d_psite && o.n_or >= 1;
     int32_t rc;
     for (int k = 0; k < n_sweeps; k++) {
         // Lattices are independent: each group runs its whole sweep before the
@@ -511,9 +561,11 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
                 const int kind = pass == 0 ? 0 : 1;
                 if (pass <= 1 && (rc = pm.begin())) return rc;
                 for (int mu = 0; mu < 4; mu++)
-                    for (int par = 0; par < 2; par++)
-                        HIPCHK(launch_phase(p.prec, kind, gph, mu, par, p.d_sweep, k, hb, kind == 0 ? exh : nullptr,
+                    for (int par = 0; par < 2; par++) {
+                        const int kk = (fused && pass == o.n_or && par == 1 && mu >= 1) ? 2 : kind;
+                        HIPCHK(launch_phase(p.prec, kk, gph, mu, par, p.d_sweep, k, hb, kind == 0 ? exh : nullptr,
                                             st));
+                    }
                 if (pass == 0 && (rc = pm.end(0, 8))) return rc;
                 if (pass == o.n_or && pass > 0 && (rc = pm.end(1, 8 * o.n_or))) return rc;
             }
@@ -522,9 +574,21 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
         if (o.record) {
             ProfMark pm{ prof_marks, st };
             if ((rc = pm.begin())) return rc;
-            HIPCHK(launch_plaq_partial(p.prec, p.grid_site(), p.d_partials, st));
-            if ((rc = pm.end(2, 1))) return rc;
-            HIPCHK(launch_reduce_final(p.grid_site(), p.d_partials, p.d_out, 1, k * p.nlat, st));
+            if (fused) {
+                // site values of the last pass; in a sweep that reunitarizes
+                // the plaquette is taken afresh from the reunitarized links
+                HIPCHK(launch_psite_partial(p.grid_psite(), p.d_partials2, st));
+                if (o.reunit_every > 0)
+                    HIPCHK(launch_plaq_partial_gated(p.prec, p.grid_site(), p.d_partials, p.d_sweep, k,
+                                                     o.reunit_every, st));
+                if ((rc = pm.end(2, 1))) return rc;
+                HIPCHK(launch_reduce_pick(p.nlat, p.d_bbeg_site, p.d_partials, p.d_bbeg_psite, p.d_partials2,
+                                          p.d_sweep, k, o.reunit_every, p.d_out, 1, k * p.nlat, st));
+            } else {
+                HIPCHK(launch_plaq_partial(p.prec, p.grid_site(), p.d_partials, st));
+                if ((rc = pm.end(2, 1))) return rc;
+                HIPCHK(launch_reduce_final(p.grid_site(), p.d_partials, p.d_out, 1, k * p.nlat, st));
+            }
         }
     }
     return SU3_OK;
@@ -601,8 +665,10 @@ static int32_t autotune(const std::vector<su3_field_s*>& fs, const double* betas
                 p.host_descs[i].seed = 12345u + (uint32_t)i;
                 p.host_descs[i].beta = betas[i];
             }
+            // every candidate starts from the same cold fields: the cost of a
+            // heat-bath pass depends on the field
             if (upload_descs(p.d_descs, p.host_descs, st) != hipSuccess ||
-                (ci == 0 && launch_init(p.prec, 0, p.grid_link(), st) != hipSuccess)) {
+                launch_init(p.prec, 0, p.grid_link(), st) != hipSuccess) {
                 rc = fail(SU3_ERR_HIP, "autotune init failed");
                 break;
             }
@@ -647,6 +713,7 @@ struct GraphEntry {
     std::string key;
     std::vector<su3_field_s*> fields;
     Plan plan;
+    bool descs_current = false;  // plan.d_descs hold plan.host_descs (only this call writes them)
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     hipStream_t capture = nullptr;
@@ -701,13 +768,14 @@ static void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1)
 // ---------------------------------------------------------------------------
 // Single-field helpers
 // ---------------------------------------------------------------------------
-static int32_t single_plan(su3_field_s* f, int out_cap)
+static int32_t single_plan(su3_field_s* f, int out_cap, bool psite = false)
 {
     std::vector<su3_field_s*> fs{ f };
     const LaunchCfg cfg = launch_choice(fs);
     if (!f->plan_ready || !(f->plan.cfg == cfg) || f->plan.out_cap < out_cap || f->plan.host_descs.empty() ||
-        f->plan.host_descs[0].aux != f->aux8 || f->plan.host_descs[0].aux2 != f->alt[0]) {
-        int32_t rc = plan_build(f->plan, fs, cfg, std::max(out_cap, 8), f->stream);
+        f->plan.host_descs[0].aux != f->aux8 || f->plan.host_descs[0].aux2 != f->alt[0] ||
+        (psite && !f->plan.d_psite)) {
+        int32_t rc = plan_build(f->plan, fs, cfg, std::max(out_cap, 8), f->stream, psite || f->plan.d_psite);
         if (rc) return rc;
         f->plan_ready = true;
     }
@@ -1003,7 +1071,7 @@ int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattic
         }
         if (!have && (rc = autotune(fs, &beta, o, f->stream))) return rc;
     }
-    if ((rc = single_plan(f, std::max(1, n_sweeps)))) return rc;
+    if ((rc = single_plan(f, std::max(1, n_sweeps), o.record))) return rc;
     Plan& p = f->plan;
     std::vector<LatDesc> d{ p.host_descs[0] };
     d[0].beta = beta;
@@ -1161,7 +1229,7 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
         ge = new GraphEntry();
         ge->key = key;
         ge->fields = v;
-        rc = plan_build(ge->plan, v, cfg, n_sweeps * n, st);
+        rc = plan_build(ge->plan, v, cfg, n_sweeps * n, st, o.record);
         if (rc) {
             drop_graph(ge);
             return rc;
@@ -1173,7 +1241,7 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
         ge = new GraphEntry();
         ge->key = key;
         ge->fields = v;
-        rc = plan_build(ge->plan, v, cfg, n_sweeps * n, st);
+        rc = plan_build(ge->plan, v, cfg, n_sweeps * n, st, o.record);
         if (!rc && hipStreamCreateWithFlags(&ge->capture, hipStreamNonBlocking) != hipSuccess)
             rc = fail(SU3_ERR_HIP, "capture stream creation failed");
         if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(SU3_ERR_HIP, "stream sync failed");
@@ -1205,12 +1273,19 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
         g_graphs.push_back(ge);
     }
     Plan& p = ge->plan;
+    bool same = ge->descs_current;
     for (int i = 0; i < n; i++) {
+        same = same && p.host_descs[i].beta == betas[i] && p.host_descs[i].seed == seeds[i] &&
+               p.host_descs[i].lid == lattice_ids[i];
         p.host_descs[i].beta = betas[i];
         p.host_descs[i].seed = seeds[i];
         p.host_descs[i].lid = lattice_ids[i];
     }
-    HIPCHK(upload_descs(p.d_descs, p.host_descs, st));
+    if (!same) {
+        ge->descs_current = false;
+        HIPCHK(upload_descs(p.d_descs, p.host_descs, st));
+        ge->descs_current = true;
+    }
     k_set_u64<<<1, 1, 0, st>>>(p.d_sweep, first_sweep);
     k_zero_u64<<<1, 256, 0, st>>>(p.d_exh, n);
     HIPCHK(hipGetLastError());

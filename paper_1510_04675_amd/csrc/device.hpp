@@ -76,11 +76,13 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32)
+        // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32) and
+        // one three-input XOR per output word (v_bitop3_b32, table 0x96)
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        c = make_uint4(__builtin_amdgcn_bitop3_b32(hi1, c.y, k0, 0x96), lo1,
+                       __builtin_amdgcn_bitop3_b32(hi0, c.w, k1, 0x96), lo0);
     }
     return c;
 }
@@ -90,9 +92,11 @@ template <> __device__ __forceinline__ double u01<double>(uint32_t x)
 {
     return ((double)(x >> 9) * 2.0 + 1.0) * 0x1p-24;
 }
+// fp32: 1 + (x >> 9) 2^-23 built from its bits, minus (1 - 2^-24); both
+// steps are exact, so the value is the same (2 (x >> 9) + 1) 2^-24.
 template <> __device__ __forceinline__ float u01<float>(uint32_t x)
 {
-    return ((float)(x >> 9) * 2.0f + 1.0f) * 0x1p-24f;
+    return __uint_as_float(0x3F800000u | (x >> 9)) - 0x1.fffffep-1f;
 }
 
 struct Rng {
@@ -185,13 +189,15 @@ __device__ __forceinline__ double fs_exp(double y)
     return ldexp(p, (int)n);
 }
 
-// math wrappers per precision
+// math wrappers per precision.  fp32 uses the hardware instructions directly
+// (the fp32 chain is never compared with fp64 bit for bit, and its draws
+// only need the accuracy of the uniforms, 2^-24): log2 times ln 2 (the
+// arguments are normal numbers in (0, 1]), square root, and sine / cosine of
+// 2 pi u, which the hardware takes in revolutions (u in (0, 1)).
 __device__ __forceinline__ double m_log(double x) { return fs_ln(x); }
-// fp32 draws: the hardware logarithm (the arguments are normal numbers in
-// (0, 1]); fp32 is never compared with fp64 bit for bit.
-__device__ __forceinline__ float m_log(float x) { return __logf(x); }
+__device__ __forceinline__ float m_log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718056f; }
 __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ float m_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 // 1 / sqrt(x): the fp64 form is the exact IEEE sequence, fp32 the hardware
 // reciprocal square root
 __device__ __forceinline__ double m_rsqrt(double x) { return 1.0 / sqrt(x); }
@@ -200,7 +206,11 @@ __device__ __forceinline__ double m_exp(double x) { return fs_exp(x); }
 __device__ __forceinline__ float m_exp(float x) { return expf(x); }
 // (cos 2 pi u, sin 2 pi u)
 __device__ __forceinline__ void m_cossin2pi(double u, double* c, double* s) { fs_cossin_2pi(u, c, s); }
-__device__ __forceinline__ void m_cossin2pi(float u, float* c, float* s) { sincospif(2.0f * u, s, c); }
+__device__ __forceinline__ void m_cossin2pi(float u, float* c, float* s)
+{
+    *c = __builtin_amdgcn_cosf(u);
+    *s = __builtin_amdgcn_sinf(u);
+}
 __device__ __forceinline__ double m_max(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ float m_max(float a, float b) { return fmaxf(a, b); }
 
@@ -651,14 +661,203 @@ template <typename R, int NC> __device__ __forceinline__ M3<R> load_at(const Lin
     return load_link<R, NC>(U.slab(mu, par), i >> 1);
 }
 
+// ---------------------------------------------------------------------------
+// 12-real fp32 staples.  Every staple term is a product of SU(3) matrices,
+// hence itself in SU(3): its rows 0 and 1 are formed by products and its row
+// 2 is conj(row0 x row1).  Rows are loaded as stored; a link's third row is
+// rebuilt only where a product reads it.
+// ---------------------------------------------------------------------------
+struct Rows2 {
+    float re[6], im[6];  // rows 0 and 1
+};
+
+__device__ __forceinline__ Rows2 load_rows2(uintptr_t slab, int cb)
+{
+    float b[12];
+    load_reals<float, 12>(slab, cb, b);
+    Rows2 r;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        r.re[k] = b[2 * k];
+        r.im[k] = b[2 * k + 1];
+    }
+    return r;
+}
+
+__device__ __forceinline__ Rows2 load_rows2_at(const Links<float, 12>& U, const Geo& g, int mu, const int n[4])
+{
+    const int i = lex_index(g, n);
+    return load_rows2(U.slab(mu, (n[0] + n[1] + n[2] + n[3]) & 1), i >> 1);
+}
+
+// entry (2, c) of an SU(3) matrix from rows 0, 1: conj(row0 x row1)_c, the
+// arithmetic of m_complete_row2
+__device__ __forceinline__ void row2_entry(const float re[6], const float im[6], int c, float& xr, float& ni)
+{
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    xr = re[c1] * re[3 + c2];
+    xr = fmaf(-im[c1], im[3 + c2], xr);
+    xr = fmaf(-re[c2], re[3 + c1], xr);
+    xr = fmaf(im[c2], im[3 + c1], xr);
+    ni = -(re[c1] * im[3 + c2]);
+    ni = fmaf(-im[c1], re[3 + c2], ni);
+    ni = fmaf(re[c2], im[3 + c1], ni);
+    ni = fmaf(im[c2], re[3 + c1], ni);
+}
+
+__device__ __forceinline__ M3<float> full_of(const Rows2& r)
+{
+    M3<float> m;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        m.re[k] = r.re[k];
+        m.im[k] = r.im[k];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) row2_entry(r.re, r.im, c, m.re[6 + c], m.im[6 + c]);
+    return m;
+}
+
+// A += S for S in SU(3) given by its rows 0, 1
+__device__ __forceinline__ void acc_su3_rows(M3<float>& A, const Rows2& S)
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        A.re[k] += S.re[k];
+        A.im[k] += S.im[k];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float xr, xi;
+        row2_entry(S.re, S.im, c, xr, xi);
+        A.re[6 + c] += xr;
+        A.im[6 + c] += xi;
+    }
+}
+
+// rows 0, 1 of X Y^+ from rows 0, 1 of X and all of Y
+__device__ __forceinline__ Rows2 rows_mul_nd(const Rows2& x, const M3<float>& y)
+{
+    Rows2 t;
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float ar = x.re[3 * r + k], ai = x.im[3 * r + k];
+                const float br = y.re[3 * s + k], bi = y.im[3 * s + k];
+                re = fmaf(ar, br, re);
+                re = fmaf(ai, bi, re);
+                im = fmaf(ai, br, im);
+                im = fmaf(-ar, bi, im);
+            }
+            t.re[3 * r + s] = re;
+            t.im[3 * r + s] = im;
+        }
+    return t;
+}
+
+// rows 0, 1 of (B A)^+ C: columns 0, 1 of B A need B whole and rows 0..2 of
+// A at columns 0, 1 only; then conj(BA)_{k r} C_{k s} summed over k.
+__device__ __forceinline__ Rows2 rows_bwd(const Rows2& a, const M3<float>& b, const M3<float>& c)
+{
+    float a2r[2], a2i[2];
+    row2_entry(a.re, a.im, 0, a2r[0], a2i[0]);
+    row2_entry(a.re, a.im, 1, a2r[1], a2i[1]);
+    float xr[3][2], xi[3][2];  // (B A)_{k r}, r = 0, 1
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const float br = b.re[3 * k + j], bi = b.im[3 * k + j];
+                const float ar = j < 2 ? a.re[3 * j + r] : a2r[r];
+                const float ai = j < 2 ? a.im[3 * j + r] : a2i[r];
+                re = fmaf(br, ar, re);
+                re = fmaf(-bi, ai, re);
+                im = fmaf(br, ai, im);
+                im = fmaf(bi, ar, im);
+            }
+            xr[k][r] = re;
+            xi[k][r] = im;
+        }
+    Rows2 t;
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int s = 0; s < 3; s++) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const float cr = c.re[3 * k + s], ci = c.im[3 * k + s];
+                re = fmaf(xr[k][r], cr, re);
+                re = fmaf(xi[k][r], ci, re);
+                im = fmaf(xr[k][r], ci, im);
+                im = fmaf(-xi[k][r], cr, im);
+            }
+            t.re[3 * r + s] = re;
+            t.im[3 * r + s] = im;
+        }
+    return t;
+}
+
+template <bool SNAP>
+__device__ __forceinline__ M3<float> staple_sum_r12(const Links<float, 12>& U, const Geo& g, int mu, const int n[4],
+                                                   M3<float>* lo)
+{
+    M3<float> A;
+    m_set_zero(A);
+    int npm[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) npm[k] = (k == mu) ? wrap_add(n[k], 1, g.L[k]) : n[k];
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) {
+            if constexpr (SNAP) *lo = A;
+            continue;
+        }
+        int npn[4] = { n[0], n[1], n[2], n[3] };
+        npn[nu] = wrap_add(n[nu], 1, g.L[nu]);
+        int nmn[4] = { n[0], n[1], n[2], n[3] };
+        nmn[nu] = wrap_add(n[nu], -1, g.L[nu]);
+        int npm_mn[4] = { npm[0], npm[1], npm[2], npm[3] };
+        npm_mn[nu] = nmn[nu];
+        {
+            // U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
+            const Rows2 a = load_rows2_at(U, g, nu, npm);
+            const M3<float> b = full_of(load_rows2_at(U, g, mu, npn));
+            const M3<float> c = full_of(load_rows2_at(U, g, nu, n));
+            acc_su3_rows(A, rows_mul_nd(rows_mul_nd(a, b), c));
+        }
+        {
+            // U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu) = (U_mu(n-nu) U_nu(n+mu-nu))^+ U_nu(n-nu)
+            const Rows2 a = load_rows2_at(U, g, nu, npm_mn);
+            const M3<float> b = full_of(load_rows2_at(U, g, mu, nmn));
+            const M3<float> c = full_of(load_rows2_at(U, g, nu, nmn));
+            acc_su3_rows(A, rows_bwd(a, b, c));
+        }
+    }
+    return A;
+}
+
 // Staple sum A_mu(n): for nu != mu ascending, the forward term
 // U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+ then the backward term
 // U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu); Re Tr(U_mu(n) A) is the sum of the
 // six plaquettes containing U_mu(n).  Computed in precision C from links of
 // precision R.
-template <typename R, int NC, typename C>
-__device__ __forceinline__ M3<C> staple_sum(const Links<R, NC>& U, const Geo& g, int mu, const int n[4])
+//
+// With SNAP, *lo receives the partial sum of the terms nu < mu (the staples
+// of the plaquettes in the planes (nu, mu), nu < mu).
+template <typename R, int NC, typename C, bool SNAP = false>
+__device__ __forceinline__ M3<C> staple_sum(const Links<R, NC>& U, const Geo& g, int mu, const int n[4],
+                                           M3<C>* lo = nullptr)
 {
+    if constexpr (NC == 12 && std::is_same<R, float>::value && std::is_same<C, float>::value)
+        return staple_sum_r12<SNAP>(U, g, mu, n, lo);
     M3<C> A;
     m_set_zero(A);
     // n + mu with mu known only at run time: selects over the unrolled
@@ -668,7 +867,10 @@ __device__ __forceinline__ M3<C> staple_sum(const Links<R, NC>& U, const Geo& g,
     for (int k = 0; k < 4; k++) npm[k] = (k == mu) ? wrap_add(n[k], 1, g.L[k]) : n[k];
 #pragma unroll
     for (int nu = 0; nu < 4; nu++) {
-        if (nu == mu) continue;
+        if (nu == mu) {
+            if constexpr (SNAP) *lo = A;
+            continue;
+        }
         int npn[4] = { n[0], n[1], n[2], n[3] };
         npn[nu] = wrap_add(n[nu], 1, g.L[nu]);
         int nmn[4] = { n[0], n[1], n[2], n[3] };

@@ -45,10 +45,10 @@ struct SiteIdx {
 // threads that run at nearly the same time on the same XCD.  The mapping
 // depends only on the logical block, and block partials are stored by
 // logical block, so sums do not depend on the hardware block order.
-__device__ __forceinline__ SiteIdx site_index(const Grid& gr)
+__device__ __forceinline__ SiteIdx site_index(const Grid& gr, int b)
 {
     SiteIdx s;
-    s.lb = logical_block(blockIdx.x, gr.nblocks, gr.remap);
+    s.lb = logical_block(b, gr.nblocks, gr.remap);
     s.l = find_lattice_m(gr.bbeg, gr.nlat, s.lb);
     const LatDesc& d = gr.descs[s.l];
     const Geo g = d.g;
@@ -146,9 +146,19 @@ __device__ __forceinline__ float retr_rows01(const float xr[6], const float xi[6
 // multiply in fp64; 12-real fields, whose third rows are by construction
 // conj(row0 x row1), form only rows 0 and 1 of the two half-plaquettes in
 // fp32 (the SU(3) identity above).
-template <typename R, int NC> __global__ void __launch_bounds__(256) k_plaq(Grid gr, double* __restrict__ partials)
+template <typename R, int NC, bool GATED = false>
+__global__ void __launch_bounds__(256) k_plaq(Grid gr, double* __restrict__ partials,
+                                              const uint64_t* __restrict__ sweep_base = nullptr, int sweep_off = 0,
+                                              int every = 0)
 {
-    const SiteIdx s = site_index(gr);
+    if constexpr (GATED) {
+        const uint64_t sw = *sweep_base + (uint64_t)sweep_off;
+        if ((sw + 1) % (uint64_t)every != 0) return;
+    }
+    // blocks loop over the logical blocks, so that a gated launch can use a
+    // small grid (most sweeps it exits at once)
+    for (int b = blockIdx.x; b < gr.nblocks; b += gridDim.x) {
+    const SiteIdx s = site_index(gr, b);
     double acc = 0.0;
     if (s.valid) {
         const LatDesc& d = gr.descs[s.l];
@@ -195,6 +205,8 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_plaq(Grid
     }
     acc = block_sum_256(acc);
     if (threadIdx.x == 0) partials[s.lb] = acc;
+    __syncthreads();  // the shared slots of block_sum_256 are reused
+    }
 }
 
 // Clover field strength: traceless part of (Q - Q^+)/8, Q the sum of the
@@ -259,7 +271,7 @@ __device__ __forceinline__ double retr_prod(const M3<double>& a, const M3<double
 // q(x) = -(1/(2 pi^2)) Re Tr[F01 F23 - F02 F13 + F03 F12]
 template <typename R, int NC> __global__ void __launch_bounds__(256) k_qtop(Grid gr, double* __restrict__ partials)
 {
-    const SiteIdx s = site_index(gr);
+    const SiteIdx s = site_index(gr, blockIdx.x);
     double acc = 0.0;
     if (s.valid) {
         const LatDesc& d = gr.descs[s.l];
@@ -289,7 +301,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_qtop(Grid
 // sum_{mu<nu} -Re Tr(F_munu F_munu) per site
 template <typename R, int NC> __global__ void __launch_bounds__(256) k_energy(Grid gr, double* __restrict__ partials)
 {
-    const SiteIdx s = site_index(gr);
+    const SiteIdx s = site_index(gr, blockIdx.x);
     double acc = 0.0;
     if (s.valid) {
         const LatDesc& d = gr.descs[s.l];
@@ -317,7 +329,7 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_energy(Gr
 template <typename R, int NC>
 __global__ void __launch_bounds__(256) k_loops(Grid gr, int lm, int ln, int mode, double* __restrict__ partials)
 {
-    const SiteIdx s = site_index(gr);
+    const SiteIdx s = site_index(gr, blockIdx.x);
     double acc[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 };
     if (s.valid) {
         const LatDesc& d = gr.descs[s.l];
@@ -367,7 +379,7 @@ __global__ void __launch_bounds__(256) k_loops(Grid gr, int lm, int ln, int mode
 // partials[logical block] (0 for padding threads).
 template <typename R, int NC> __global__ void __launch_bounds__(256) k_max_splaq(Grid gr, double* __restrict__ partials)
 {
-    const SiteIdx s = site_index(gr);
+    const SiteIdx s = site_index(gr, blockIdx.x);
     double h = 0.0;
     if (s.valid) {
         const LatDesc& d = gr.descs[s.l];
@@ -394,6 +406,55 @@ template <typename R, int NC> __global__ void __launch_bounds__(256) k_max_splaq
     if (threadIdx.x == 0) partials[s.lb] = h;
 }
 
+// Block partials of the plaquette site values that the last overrelaxation
+// pass of a sweep wrote (3 Vh doubles per lattice): block b of a lattice adds
+// values [1024 b, 1024 b + 1024), four consecutive ones per thread, in a
+// fixed order that does not depend on any launch shape.
+__global__ void __launch_bounds__(256) k_psite(Grid gr, double* __restrict__ partials)
+{
+    const int lb = blockIdx.x;
+    const int l = find_lattice_m(gr.bbeg, gr.nlat, lb);
+    const LatDesc& d = gr.descs[l];
+    const size_t n = (size_t)3 * d.g.Vh;
+    const size_t i0 = (size_t)(lb - gr.bbeg[l]) * 1024 + 4 * (size_t)threadIdx.x;
+    double v = 0.0;
+    if (i0 + 4 <= n) {
+        // 3 Vh is a multiple of 4 and every lattice's values start 32-byte
+        // aligned: two 16-byte loads
+        const v2d a = vload<true, v2d>((uintptr_t)(d.psite + i0));
+        const v2d b = vload<true, v2d>((uintptr_t)(d.psite + i0 + 2));
+        v = ((a.x + a.y) + b.x) + b.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (i0 + k < n) v += d.psite[i0 + k];
+    }
+    v = block_sum_256(v);
+    if (threadIdx.x == 0) partials[lb] = v;
+}
+
+// One block per lattice: the partials of (bbeg_a, pa) in sweeps that
+// reunitarize, else those of (bbeg_b, pb), added in a fixed order.
+__global__ void __launch_bounds__(256) k_reduce_pick(const int* __restrict__ bbeg_a, const double* __restrict__ pa,
+                                                     const int* __restrict__ bbeg_b, const double* __restrict__ pb,
+                                                     const uint64_t* __restrict__ sweep_base, int sweep_off, int every,
+                                                     double* __restrict__ out, int stride, int off)
+{
+    const int l = blockIdx.x;
+    bool use_a = false;
+    if (every > 0) {
+        const uint64_t sw = *sweep_base + (uint64_t)sweep_off;
+        use_a = (sw + 1) % (uint64_t)every == 0;
+    }
+    const int* bbeg = use_a ? bbeg_a : bbeg_b;
+    const double* p = use_a ? pa : pb;
+    const int b0 = bbeg[l], b1 = bbeg[l + 1];
+    double v = 0.0;
+    for (int k = b0 + (int)threadIdx.x; k < b1; k += 256) v += p[k];
+    v = block_sum_256(v);
+    if (threadIdx.x == 0) out[(size_t)l * stride + off] = v;
+}
+
 // One block per lattice: out[l * stride + off] = sum of its partials.
 __global__ void __launch_bounds__(256) k_reduce_final(const int* __restrict__ bbeg, const double* __restrict__ partials,
                                                       double* __restrict__ out, int stride, int off)
@@ -418,6 +479,32 @@ hipError_t launch_plaq_partial(int prec, const Grid& gr, double* partials, hipSt
 {
     if (gr.nblocks <= 0) return hipSuccess;
     DISPATCH_PREC_M(prec, (k_plaq<R, NC><<<gr.nblocks, 256, 0, st>>>(gr, partials)));
+    return hipGetLastError();
+}
+
+hipError_t launch_plaq_partial_gated(int prec, const Grid& gr, double* partials, const uint64_t* sweep_base,
+                                     int sweep_off, int every, hipStream_t st)
+{
+    if (gr.nblocks <= 0) return hipSuccess;
+    if (every <= 0) return hipErrorInvalidValue;
+    const int nb = gr.nblocks < 2048 ? gr.nblocks : 2048;
+    DISPATCH_PREC_M(prec, (k_plaq<R, NC, true><<<nb, 256, 0, st>>>(gr, partials, sweep_base, sweep_off, every)));
+    return hipGetLastError();
+}
+
+hipError_t launch_psite_partial(const Grid& gr, double* partials, hipStream_t st)
+{
+    if (gr.nblocks <= 0) return hipSuccess;
+    k_psite<<<gr.nblocks, 256, 0, st>>>(gr, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_pick(int nlat, const int* bbeg_a, const double* pa, const int* bbeg_b, const double* pb,
+                              const uint64_t* sweep_base, int sweep_off, int every, double* out, int stride, int off,
+                              hipStream_t st)
+{
+    if (nlat <= 0) return hipSuccess;
+    k_reduce_pick<<<nlat, 256, 0, st>>>(bbeg_a, pa, bbeg_b, pb, sweep_base, sweep_off, every, out, stride, off);
     return hipGetLastError();
 }
 

@@ -10,9 +10,11 @@ hipError_t launch_phase_f32(int prec, int kind, const Grid& gr, int mu, int par,
 {
     if (prec == PREC_F32) {
         if (kind == 0) return launch_phase_t<float, 18, 0>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
+        if (kind == 2) return launch_phase_t<float, 18, 2>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
         return launch_phase_t<float, 18, 1>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
     }
     if (kind == 0) return launch_phase_t<float, 12, 0>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
+    if (kind == 2) return launch_phase_t<float, 12, 2>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
     return launch_phase_t<float, 12, 1>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
 }
 

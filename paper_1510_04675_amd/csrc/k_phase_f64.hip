@@ -9,6 +9,7 @@ hipError_t launch_phase_f64(int kind, const Grid& gr, int mu, int par, const uin
                             HbArgs hb, unsigned long long* exhausted, hipStream_t st)
 {
     if (kind == 0) return launch_phase_t<double, 18, 0>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
+    if (kind == 2) return launch_phase_t<double, 18, 2>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
     return launch_phase_t<double, 18, 1>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
 }
 

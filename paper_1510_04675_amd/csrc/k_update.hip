@@ -24,7 +24,7 @@ hipError_t launch_phase(int prec, int kind, const Grid& gr, int mu, int par, con
                         int sweep_off, HbArgs hb, unsigned long long* exhausted, hipStream_t st)
 {
     if (gr.nblocks <= 0) return hipSuccess;
-    if (kind != 0 && kind != 1) return hipErrorInvalidValue;
+    if (kind < 0 || kind > 2) return hipErrorInvalidValue;
     if (prec == PREC_F64) return launch_phase_f64(kind, gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
     if (prec == PREC_F32 || prec == PREC_F32_R12)
         return launch_phase_f32(prec, kind, gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
@@ -40,10 +40,10 @@ struct LinkIdx {
     bool valid;
 };
 
-__device__ __forceinline__ LinkIdx link_index(const Grid& gr)
+__device__ __forceinline__ LinkIdx link_index(const Grid& gr, int b)
 {
     LinkIdx x;
-    const int lb = logical_block(blockIdx.x, gr.nblocks, gr.remap);
+    const int lb = logical_block(b, gr.nblocks, gr.remap);
     x.l = find_lattice(gr.bbeg, gr.nlat, lb);
     const int Vh = gr.descs[x.l].g.Vh;
     const int e = (lb - gr.bbeg[x.l]) * (int)blockDim.x + (int)threadIdx.x;
@@ -76,7 +76,7 @@ __device__ __forceinline__ M3<double> haar_from_rng(const Rng& rng, uint32_t pur
 
 template <typename R, int NC> __global__ void __launch_bounds__(256) k_init(Grid gr, int hot)
 {
-    const LinkIdx x = link_index(gr);
+    const LinkIdx x = link_index(gr, blockIdx.x);
     if (!x.valid) return;
     const LatDesc& d = gr.descs[x.l];
     const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
@@ -100,14 +100,17 @@ __global__ void __launch_bounds__(256) k_reunit(Grid gr, const uint64_t* __restr
         const uint64_t s = *sweep_base + (uint64_t)sweep_off;
         if ((s + 1) % (uint64_t)every != 0) return;
     }
-    const LinkIdx x = link_index(gr);
-    if (!x.valid) return;
-    const LatDesc& d = gr.descs[x.l];
-    const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
-    const uintptr_t s = U.slab(x.mu, x.par);
-    M3<double> m = m_cast<R, double>(load_link<R, NC>(s, x.cb));
-    m_reunit(m);
-    store_link<R, NC>(s, x.cb, m_cast<double, R>(m));
+    // a small grid loops over the logical blocks (most sweeps exit above)
+    for (int b = blockIdx.x; b < gr.nblocks; b += gridDim.x) {
+        const LinkIdx x = link_index(gr, b);
+        if (!x.valid) continue;
+        const LatDesc& d = gr.descs[x.l];
+        const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
+        const uintptr_t s = U.slab(x.mu, x.par);
+        M3<double> m = m_cast<R, double>(load_link<R, NC>(s, x.cb));
+        m_reunit(m);
+        store_link<R, NC>(s, x.cb, m_cast<double, R>(m));
+    }
 }
 
 // U_mu(n) -> Om(n) U_mu(n) Om(n+mu)^+, Om Haar-random per site from Philox
@@ -115,7 +118,7 @@ __global__ void __launch_bounds__(256) k_reunit(Grid gr, const uint64_t* __restr
 // needs, so the update is in place.
 template <typename R, int NC> __global__ void __launch_bounds__(256) k_gauge(Grid gr, uint32_t seed)
 {
-    const LinkIdx x = link_index(gr);
+    const LinkIdx x = link_index(gr, blockIdx.x);
     if (!x.valid) return;
     const LatDesc& d = gr.descs[x.l];
     const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
@@ -151,7 +154,8 @@ hipError_t launch_reunit(int prec, const Grid& gr, const uint64_t* sweep_base, i
                          hipStream_t st)
 {
     if (gr.nblocks <= 0) return hipSuccess;
-    DISPATCH_PREC(prec, (k_reunit<R, NC><<<gr.nblocks, gr.block, 0, st>>>(gr, sweep_base, sweep_off, every)));
+    const int nb = (every > 0 && gr.nblocks > 4096) ? 4096 : gr.nblocks;
+    DISPATCH_PREC(prec, (k_reunit<R, NC><<<nb, gr.block, 0, st>>>(gr, sweep_base, sweep_off, every)));
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ struct LatDesc {
     uint32_t seed, lid;
     int tile[3];   // (ty, tz, tt): site tile of the phase kernels (divisors of L1, L2, L3)
     int mtile[3];  // (ty, tz, tt): site tile of the measurement kernels, fixed by the extents
+    double* psite; // plaquette site values of the last overrelaxation pass (3 x Vh), or NULL
 };
 
 // Block partition: lattice l owns logical blocks [bbeg[l], bbeg[l+1]).
@@ -90,8 +91,11 @@ struct HbArgs {
 
 // --- update kernels (k_update.hip) -----------------------------------------
 // One checkerboard phase (mu, parity) of the heat bath (kind 0) or the
-// overrelaxation (kind 1).  Work unit: one link of that direction and parity
-// per thread, bbeg counts ceil(Vh / block) blocks per lattice.
+// overrelaxation (kind 1).  Kind 2 is overrelaxation that also writes, for
+// the odd-parity phases mu = 1, 2, 3 of a sweep's last pass, each site's
+// share of the plaquette sum into psite (see k_phase).  Work unit: one link
+// of that direction and parity per thread, bbeg counts ceil(Vh / block)
+// blocks per lattice.
 hipError_t launch_phase(int prec, int kind, const Grid& gr, int mu, int par, const uint64_t* sweep_base,
                         int sweep_off, HbArgs hb, unsigned long long* exhausted, hipStream_t st);
 hipError_t launch_phase_f64(int kind, const Grid& gr, int mu, int par, const uint64_t* sweep_base, int sweep_off,
@@ -119,6 +123,20 @@ hipError_t launch_check(int prec, const Geo& g, const void* U, size_t cs, double
 // Sum over sites and planes of 1 - (1/3) Re Tr U_munu(n) in fp64.  Work unit:
 // one site per thread, bbeg counts ceil(V / 256) blocks per lattice.
 hipError_t launch_plaq_partial(int prec, const Grid& gr, double* partials, hipStream_t st);
+// The same, done only in sweeps s = *sweep_base + sweep_off with
+// (s + 1) % every == 0 (those that reunitarize); other sweeps exit at once.
+hipError_t launch_plaq_partial_gated(int prec, const Grid& gr, double* partials, const uint64_t* sweep_base,
+                                     int sweep_off, int every, hipStream_t st);
+// Block partials of the plaquette site values psite of each lattice (3 Vh
+// doubles, 1024 per block in a fixed order): bbeg counts ceil(3 Vh / 1024)
+// blocks per lattice.
+hipError_t launch_psite_partial(const Grid& gr, double* partials, hipStream_t st);
+// out[l * stride + off] = sum of lattice l's partials from (bbeg_a, pa) if
+// sweep *sweep_base + sweep_off reunitarizes (every > 0), else from
+// (bbeg_b, pb).
+hipError_t launch_reduce_pick(int nlat, const int* bbeg_a, const double* pa, const int* bbeg_b, const double* pb,
+                              const uint64_t* sweep_base, int sweep_off, int every, double* out, int stride, int off,
+                              hipStream_t st);
 // out[l * stride + off] = sum of partials of lattice l (fixed order).
 hipError_t launch_reduce_final(const Grid& gr, const double* partials, double* out, int stride, int off,
                                hipStream_t st);

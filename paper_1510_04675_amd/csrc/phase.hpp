@@ -44,8 +44,12 @@ template <typename R>
 __device__ __forceinline__ bool draw_g0(const Rng& rng, R alpha, int mu, int sg, int h, const HbArgs& hb, R& g0)
 {
     // fp64 divides by alpha exactly as the reference order does; fp32 scales
-    // by the reciprocal
-    const R ia = R(1) / alpha;
+    // by the hardware reciprocal
+    R ia;
+    if constexpr (std::is_same<R, double>::value)
+        ia = R(1) / alpha;
+    else
+        ia = __builtin_amdgcn_rcpf(alpha);
     for (int t = 0; t < hb.max_tries; t++) {
         const uint4 w = rng.draw(ctr_word(P_HB, mu, sg, h, t));
         const R u0 = u01<R>(w.x), u1 = u01<R>(w.y), u2 = u01<R>(w.z), u3 = u01<R>(w.w);
@@ -72,6 +76,70 @@ __device__ __forceinline__ bool draw_g0(const Rng& rng, R alpha, int mu, int sg,
                 g0 = x;
                 return true;
             }
+        }
+    }
+    return false;
+}
+
+// fp32 Kennedy-Pendleton heat bath: the link-independent part of the first
+// kPreTrials trials of every subgroup (hit 0) and of their directions is
+// computed before the staple, while its loads are in flight.  Per trial:
+// e = -(ln u0 + cos^2(2 pi u1) ln u2), so that delta = e / alpha, and u3^2;
+// per direction: cos(theta), sin(theta) cos(phi), sin(theta) sin(phi).
+constexpr int kPreTrials = 2;
+struct KpPre {
+    float e[3][kPreTrials > 0 ? kPreTrials : 1], a[3][kPreTrials > 0 ? kPreTrials : 1];
+    float ct[3], sc[3], ss[3];
+};
+
+__device__ __forceinline__ void kp_trial_parts(const Rng& rng, int mu, int sg, int t, float& e, float& a)
+{
+    const uint4 w = rng.draw(ctr_word(P_HB, mu, sg, 0, t));
+    float cs, sn;
+    m_cossin2pi(u01<float>(w.y), &cs, &sn);
+    e = -(m_log(u01<float>(w.x)) + cs * cs * m_log(u01<float>(w.z)));
+    const float u3 = u01<float>(w.w);
+    a = u3 * u3;
+}
+
+__device__ __forceinline__ void kp_precompute(const Rng& rng, int mu, KpPre& p)
+{
+#pragma unroll
+    for (int sg = 0; sg < 3; sg++) {
+#pragma unroll
+        for (int t = 0; t < kPreTrials; t++) kp_trial_parts(rng, mu, sg, t, p.e[sg][t], p.a[sg][t]);
+        const uint4 w = rng.draw(ctr_word(P_HB_DIR, mu, sg, 0, 0));
+        const float ct = 2.0f * u01<float>(w.x) - 1.0f;
+        const float stt = m_sqrt(m_max(0.0f, 1.0f - ct * ct));
+        float cp, sp;
+        m_cossin2pi(u01<float>(w.y), &cp, &sp);
+        p.ct[sg] = ct;
+        p.sc[sg] = stt * cp;
+        p.ss[sg] = stt * sp;
+    }
+}
+
+// g0 for the precomputed case: the same trials in the same order as draw_g0.
+__device__ __forceinline__ bool draw_g0_pre(const Rng& rng, float alpha, int mu, int sg, const HbArgs& hb,
+                                            const KpPre& p, float& g0)
+{
+    const float ia = __builtin_amdgcn_rcpf(alpha);
+#pragma unroll
+    for (int t = 0; t < kPreTrials; t++) {
+        if (t >= hb.max_tries) return false;
+        const float delta = p.e[sg][t] * ia;
+        if (p.a[sg][t] <= 1.0f - 0.5f * delta) {
+            g0 = 1.0f - delta;
+            return true;
+        }
+    }
+    for (int t = kPreTrials; t < hb.max_tries; t++) {
+        float e, a;
+        kp_trial_parts(rng, mu, sg, t, e, a);
+        const float delta = e * ia;
+        if (a <= 1.0f - 0.5f * delta) {
+            g0 = 1.0f - delta;
+            return true;
         }
     }
     return false;
@@ -111,14 +179,22 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
     int n[4];
     tiled_coords(g, d.tile, w, par, n);
     const int cb = lex_index(g, n) >> 1;
-    const M3<R> A = staple_sum<R, NC, R>(U, g, mu, n);
+    Rng rng{ d.seed, d.lid, (uint32_t)lex_index(g, n), 0 };
+    if (KIND == 0) rng.step = *sweep_base + (uint64_t)sweep_off;
+    // fp32 KP: draws of hit 0 ahead of the staple (uniform branch)
+    constexpr bool kPre = !kF64 && KIND == 0 && kPreTrials >= 0;
+    const bool pre = kPre && hb.sampler == 0 && kPreTrials > 0;
+    KpPre kp;
+    if constexpr (kPre)
+        if (pre) kp_precompute(rng, mu, kp);
+
+    M3<R> Alo;  // kind 2: the staples of the planes (nu, mu), nu < mu
+    const M3<R> A = staple_sum<R, NC, R, KIND == 2>(U, g, mu, n, &Alo);
     const uintptr_t s = U.slab(mu, par);
     M3<R> u = load_link<R, NC, true>(s, cb);
     M3<R> W = m_mul(u, A);
-
-    Rng rng{ d.seed, d.lid, (uint32_t)lex_index(g, n), 0 };
-    if (KIND == 0) rng.step = *sweep_base + (uint64_t)sweep_off;
     const R beta = (R)d.beta;
+    const float b23 = (float)(d.beta * (2.0 / 3.0));  // fp32 alpha = (2 beta / 3) k
     const int nh = (KIND == 0) ? hb.n_hits : 1;
 
     for (int h = 0; h < nh; h++) {
@@ -153,14 +229,26 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
                 if (!(k > R(0))) continue;
                 Q4<R> r;
                 if (KIND == 0) {
-                    const R alpha = R(2) * beta * k / R(3);
+                    const R alpha = b23 * k;
                     R g0;
-                    if (!draw_g0<R>(rng, alpha, mu, sg, h, hb, g0)) {
-                        if (exhausted) atomicAdd(exhausted + l, 1ull);
-                        continue;
-                    }
                     R q[4];
-                    draw_dir<R>(rng, mu, sg, h, g0, q);
+                    if (pre && h == 0) {
+                        if (!draw_g0_pre(rng, alpha, mu, sg, hb, kp, g0)) {
+                            if (exhausted) atomicAdd(exhausted + l, 1ull);
+                            continue;
+                        }
+                        const R sr = m_sqrt(m_max(R(0), R(1) - g0 * g0));
+                        q[0] = g0;
+                        q[1] = sr * kp.sc[sg];
+                        q[2] = sr * kp.ss[sg];
+                        q[3] = sr * kp.ct[sg];
+                    } else {
+                        if (!draw_g0<R>(rng, alpha, mu, sg, h, hb, g0)) {
+                            if (exhausted) atomicAdd(exhausted + l, 1ull);
+                            continue;
+                        }
+                        draw_dir<R>(rng, mu, sg, h, g0, q);
+                    }
                     r = q_mul(Q4<R>{ q[0], q[1], q[2], q[3] }, q_conj(v));
                 } else {
                     const Q4<R> vd = q_conj(v);
@@ -175,6 +263,26 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
     // before every store: rounding in a 12-real record would otherwise grow,
     // because the rebuilt third row feeds back into rows 0 and 1.
     if constexpr (!kF64) m_reunit(u);
+    if constexpr (KIND == 2) {
+        // Plaquette sum of the sweep, formed in its last pass: a phase (mu,
+        // odd) with mu >= 1 is the last update of every plaquette in the
+        // planes (nu, mu), nu < mu, and each of those plaquettes holds
+        // exactly one odd-site link U_mu, whose staple has it as a term.  So
+        // Re Tr(U_mu A_lo) over the odd sites, A_lo the staples with nu < mu,
+        // counts each plaquette of those planes once, and the phases mu = 1,
+        // 2, 3 cover all six planes.  Per site: the 2 mu plaquettes'
+        // sum of 1 - (1/3) Re Tr U_p, traced in fp64 from the stored link.
+        if (par == 1 && mu >= 1 && d.psite) {
+            const M3<double> ud = m_cast<R, double>(u);
+            const M3<double> ad = m_cast<R, double>(Alo);
+            double t = 0.0;
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) t += ud.re[3 * r + k] * ad.re[3 * k + r] - ud.im[3 * r + k] * ad.im[3 * k + r];
+            d.psite[(size_t)(mu - 1) * g.Vh + cb] = (double)(2 * mu) - t / 3.0;
+        }
+    }
     store_link<R, NC, true>(s, cb, u);
 }
 
@@ -201,7 +309,7 @@ template <typename R, int NC, int KIND>
 static hipError_t launch_phase_t(const Grid& gr, int mu, int par, const uint64_t* sb, int so, HbArgs hb,
                                  unsigned long long* ex, hipStream_t st)
 {
-    const size_t lds = (KIND == 1) ? or_lds_bytes(gr.block) : 0;
+    const size_t lds = (KIND != 0) ? or_lds_bytes(gr.block) : 0;
     k_phase<R, NC, KIND><<<gr.nblocks, gr.block, lds, st>>>(gr, mu, par, sb, so, hb, ex);
     return hipGetLastError();
 }

@@ -1,8 +1,10 @@
 """The allocation-free sweep entry point against the allocating one, through
-the C ABI: same arguments, same kernels, so the links, the plaquette
-history and the exhausted-draw count must be bitwise equal.  Two calls in a
-row share the device scratch array, the second on a smaller lattice, so a
-state left over from the first call would show."""
+the C ABI: same arguments, same update kernels, so the links and the
+exhausted-draw count must be bitwise equal; its plaquette history comes from
+the standalone plaquette kernel instead of the last overrelaxation pass and
+must agree to rounding (1e-13 fp64, 1e-7 fp32).  Two calls in a row share
+the device scratch array, the second on a smaller lattice, so a state left
+over from the first call would show."""
 import ctypes as C
 
 import numpy as np
@@ -35,7 +37,7 @@ def test_noalloc_sweeps_equal_allocating_sweeps(m, prec):
         a, b = _pair(m, dims, prec, 17, 3)
         ha = m.su3_sweep_hb_or(a, beta, 17, 3, first, n, params)
         hb = m.su3_sweep_hb_or_noalloc(b, beta, 17, 3, first, n, params)
-        assert np.array_equal(ha, hb), (dims, ha, hb)
+        assert np.max(np.abs(ha - hb)) < (1e-13 if prec == "fp64" else 1e-7), (dims, ha, hb)
         assert np.array_equal(m.su3_field_to_host(a), m.su3_field_to_host(b)), dims
         assert m.su3_last_exhausted(a) == m.su3_last_exhausted(b)
         if beta == 1.0:
