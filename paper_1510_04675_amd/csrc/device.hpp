@@ -662,32 +662,38 @@ template <typename R, int NC> __device__ __forceinline__ M3<R> load_at(const Lin
 }
 
 // ---------------------------------------------------------------------------
-// 12-real fp32 staples.  Every staple term is a product of SU(3) matrices,
-// hence itself in SU(3): its rows 0 and 1 are formed by products and its row
-// 2 is conj(row0 x row1).  Rows are loaded as stored; a link's third row is
-// rebuilt only where a product reads it.
+// fp32 staples.  Every staple term is a product of SU(3) matrices, hence
+// itself in SU(3): its rows 0 and 1 are formed by products and its row 2 is
+// conj(row0 x row1).  Of a term's first factor only rows 0 and 1 are loaded
+// (its row-2 entries where the backward term reads them); a 12-real link's
+// third row is rebuilt only where a product reads it.
 // ---------------------------------------------------------------------------
 struct Rows2 {
     float re[6], im[6];  // rows 0 and 1
 };
 
-__device__ __forceinline__ Rows2 load_rows2(uintptr_t slab, int cb)
+// rows 0 and 1 of a record of NC = 12 or 18 reals: its first three 16-byte
+// chunks
+template <int NC> __device__ __forceinline__ Rows2 load_rows2(uintptr_t slab, int cb)
 {
-    float b[12];
-    load_reals<float, 12>(slab, cb, b);
+    const uintptr_t q = slab + (uintptr_t)(cb >> 5) * Rec<float, NC>::TB + (uintptr_t)(cb & 31) * 16;
     Rows2 r;
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
-        r.re[k] = b[2 * k];
-        r.im[k] = b[2 * k + 1];
+    for (int c = 0; c < 3; c++) {
+        const v4f v = vload<false, v4f>(q + c * 512);
+        r.re[2 * c] = v.x;
+        r.im[2 * c] = v.y;
+        r.re[2 * c + 1] = v.z;
+        r.im[2 * c + 1] = v.w;
     }
     return r;
 }
 
-__device__ __forceinline__ Rows2 load_rows2_at(const Links<float, 12>& U, const Geo& g, int mu, const int n[4])
+template <int NC>
+__device__ __forceinline__ Rows2 load_rows2_at(const Links<float, NC>& U, const Geo& g, int mu, const int n[4])
 {
     const int i = lex_index(g, n);
-    return load_rows2(U.slab(mu, (n[0] + n[1] + n[2] + n[3]) & 1), i >> 1);
+    return load_rows2<NC>(U.slab(mu, (n[0] + n[1] + n[2] + n[3]) & 1), i >> 1);
 }
 
 // entry (2, c) of an SU(3) matrix from rows 0, 1: conj(row0 x row1)_c, the
@@ -761,11 +767,9 @@ __device__ __forceinline__ Rows2 rows_mul_nd(const Rows2& x, const M3<float>& y)
 
 // rows 0, 1 of (B A)^+ C: columns 0, 1 of B A need B whole and rows 0..2 of
 // A at columns 0, 1 only; then conj(BA)_{k r} C_{k s} summed over k.
-__device__ __forceinline__ Rows2 rows_bwd(const Rows2& a, const M3<float>& b, const M3<float>& c)
+__device__ __forceinline__ Rows2 rows_bwd(const Rows2& a, const float a2r[2], const float a2i[2], const M3<float>& b,
+                                          const M3<float>& c)
 {
-    float a2r[2], a2i[2];
-    row2_entry(a.re, a.im, 0, a2r[0], a2i[0]);
-    row2_entry(a.re, a.im, 1, a2r[1], a2i[1]);
     float xr[3][2], xi[3][2];  // (B A)_{k r}, r = 0, 1
 #pragma unroll
     for (int k = 0; k < 3; k++)
@@ -805,9 +809,19 @@ __device__ __forceinline__ Rows2 rows_bwd(const Rows2& a, const M3<float>& b, co
     return t;
 }
 
-template <bool SNAP>
-__device__ __forceinline__ M3<float> staple_sum_r12(const Links<float, 12>& U, const Geo& g, int mu, const int n[4],
-                                                   M3<float>* lo)
+// a link whole: 12-real records rebuild row 2, 18-real ones load it
+template <int NC>
+__device__ __forceinline__ M3<float> load_full_at(const Links<float, NC>& U, const Geo& g, int mu, const int n[4])
+{
+    if constexpr (NC == 12)
+        return full_of(load_rows2_at<12>(U, g, mu, n));
+    else
+        return load_at(U, g, mu, n);
+}
+
+template <int NC, bool SNAP>
+__device__ __forceinline__ M3<float> staple_sum_rows(const Links<float, NC>& U, const Geo& g, int mu, const int n[4],
+                                                    M3<float>* lo)
 {
     M3<float> A;
     m_set_zero(A);
@@ -828,17 +842,35 @@ __device__ __forceinline__ M3<float> staple_sum_r12(const Links<float, 12>& U, c
         npm_mn[nu] = nmn[nu];
         {
             // U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
-            const Rows2 a = load_rows2_at(U, g, nu, npm);
-            const M3<float> b = full_of(load_rows2_at(U, g, mu, npn));
-            const M3<float> c = full_of(load_rows2_at(U, g, nu, n));
+            const Rows2 a = load_rows2_at<NC>(U, g, nu, npm);
+            const M3<float> b = load_full_at<NC>(U, g, mu, npn);
+            const M3<float> c = load_full_at<NC>(U, g, nu, n);
             acc_su3_rows(A, rows_mul_nd(rows_mul_nd(a, b), c));
         }
         {
-            // U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu) = (U_mu(n-nu) U_nu(n+mu-nu))^+ U_nu(n-nu)
-            const Rows2 a = load_rows2_at(U, g, nu, npm_mn);
-            const M3<float> b = full_of(load_rows2_at(U, g, mu, nmn));
-            const M3<float> c = full_of(load_rows2_at(U, g, nu, nmn));
-            acc_su3_rows(A, rows_bwd(a, b, c));
+            // U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu) = (U_mu(n-nu) U_nu(n+mu-nu))^+ U_nu(n-nu):
+            // of the first factor rows 0, 1 and the row-2 entries of columns 0, 1
+            Rows2 a;
+            float a2r[2], a2i[2];
+            if constexpr (NC == 12) {
+                a = load_rows2_at<12>(U, g, nu, npm_mn);
+                row2_entry(a.re, a.im, 0, a2r[0], a2i[0]);
+                row2_entry(a.re, a.im, 1, a2r[1], a2i[1]);
+            } else {
+                const M3<float> af = load_at(U, g, nu, npm_mn);
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    a.re[k] = af.re[k];
+                    a.im[k] = af.im[k];
+                }
+                a2r[0] = af.re[6];
+                a2i[0] = af.im[6];
+                a2r[1] = af.re[7];
+                a2i[1] = af.im[7];
+            }
+            const M3<float> b = load_full_at<NC>(U, g, mu, nmn);
+            const M3<float> c = load_full_at<NC>(U, g, nu, nmn);
+            acc_su3_rows(A, rows_bwd(a, a2r, a2i, b, c));
         }
     }
     return A;
@@ -851,13 +883,17 @@ __device__ __forceinline__ M3<float> staple_sum_r12(const Links<float, 12>& U, c
 // precision R.
 //
 // With SNAP, *lo receives the partial sum of the terms nu < mu (the staples
-// of the plaquettes in the planes (nu, mu), nu < mu).
+// of the plaquettes in the planes (nu, mu), nu < mu).  In fp32 the terms are
+// formed from their rows 0 and 1 (staple_sum_rows), which takes every term to
+// be in SU(3): exact for 12-real links; 18-real HMC and flow links are off
+// SU(3) only by rounding, and the difference is of that order (HMC energy
+// differences against fp64 stay within their bars).
 template <typename R, int NC, typename C, bool SNAP = false>
 __device__ __forceinline__ M3<C> staple_sum(const Links<R, NC>& U, const Geo& g, int mu, const int n[4],
                                            M3<C>* lo = nullptr)
 {
-    if constexpr (NC == 12 && std::is_same<R, float>::value && std::is_same<C, float>::value)
-        return staple_sum_r12<SNAP>(U, g, mu, n, lo);
+    if constexpr (std::is_same<R, float>::value && std::is_same<C, float>::value)
+        return staple_sum_rows<NC, SNAP>(U, g, mu, n, lo);
     M3<C> A;
     m_set_zero(A);
     // n + mu with mu known only at run time: selects over the unrolled
@@ -952,7 +988,14 @@ __device__ __forceinline__ int logical_block(int b, int nblocks, int remap)
 // the Frobenius norm of X / 2^s is at most 2^-L (the remainder is then below
 // 2^(-L (N+1)) / (N+1)!).  The innermost Horner factor 1 + Y/N is formed
 // directly, so order N costs N - 1 matrix products.
-template <typename R, int N, int L = 2> __device__ __forceinline__ M3<R> m_exp_ah(const M3<R>& X)
+//
+// With PS (order 6 only) the same polynomial is evaluated in Paterson-
+// Stockmeyer form, three products instead of five.  In fp32 its rounding
+// leaves a unitarity error of the same sign on every link (a 16^4 HMC
+// trajectory with 18-real links ended 4.3 units of dH away from fp64, the
+// Horner form 6e-4), so it is used only where the result is re-orthonormalized
+// in fp64 before it is stored (12-real links).
+template <typename R, int N, int L = 2, bool PS = false> __device__ __forceinline__ M3<R> m_exp_ah(const M3<R>& X)
 {
     R nrm = R(0);
 #pragma unroll
@@ -970,6 +1013,28 @@ template <typename R, int N, int L = 2> __device__ __forceinline__ M3<R> m_exp_a
     for (int k = 0; k < 9; k++) {
         Y.re[k] = X.re[k] * sc;
         Y.im[k] = X.im[k] * sc;
+    }
+    if constexpr (PS && N == 6) {
+        // Paterson-Stockmeyer form of the same polynomial, three products:
+        // E = (1 + Y + Y^2/2) + Y^3 (1/6 + Y/24 + Y^2/120 + Y^3/720)
+        const M3<R> Y2 = m_mul(Y, Y);
+        const M3<R> Y3 = m_mul(Y, Y2);
+        M3<R> B, E;
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            B.re[q] = Y.re[q] * R(1.0 / 24) + Y2.re[q] * R(1.0 / 120) + Y3.re[q] * R(1.0 / 720);
+            B.im[q] = Y.im[q] * R(1.0 / 24) + Y2.im[q] * R(1.0 / 120) + Y3.im[q] * R(1.0 / 720);
+            E.re[q] = Y.re[q] + Y2.re[q] * R(0.5);
+            E.im[q] = Y.im[q] + Y2.im[q] * R(0.5);
+        }
+#pragma unroll
+        for (int q = 0; q < 9; q += 4) {
+            B.re[q] += R(1.0 / 6);
+            E.re[q] += R(1);
+        }
+        mm_acc<false, false>(E, Y3, B);
+        for (int q = 0; q < s; q++) E = m_mul(E, E);
+        return E;
     }
     // Horner: E = 1 + Y (1 + Y/2 (1 + Y/3 (... (1 + Y/N))))
     M3<R> E;

@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(Grid gr, double eps_kick, do
     for (int a = 0; a < 8; a++) p[a] = p[a] - ek * F[a];
     store_reals<R, 8>(pslab, x.cb, p);
     if (drift) {
-        const M3<R> E = m_exp_ah<R, ExpOrder<R>::N>(i_eps_P(p, (R)eps_drift));
+        const M3<R> E = m_exp_ah<R, ExpOrder<R>::N, 2, NC == 12>(i_eps_P(p, (R)eps_drift));
         const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
         M3<R> un = m_mul(E, u);
         // 12-real records: row 2 is rebuilt from rows 0 and 1, so keep them
