@@ -819,9 +819,41 @@ __device__ __forceinline__ M3<float> load_full_at(const Links<float, NC>& U, con
         return load_at(U, g, mu, n);
 }
 
-template <int NC, bool SNAP>
-__device__ __forceinline__ M3<float> staple_sum_rows(const Links<float, NC>& U, const Geo& g, int mu, const int n[4],
-                                                    M3<float>* lo)
+// Where a staple link sits relative to the updated link's site n: n itself,
+// n + e_0, n - e_0, or elsewhere (a loader may serve the first three from
+// on-chip copies).
+enum NbKind { NB_SAME = 0, NB_XP = 1, NB_XM = 2, NB_OTHER = 3 };
+
+// Staple links straight from the field.
+template <int NC> struct GlobalLd {
+    const Links<float, NC>& U;
+    const Geo& g;
+    __device__ __forceinline__ Rows2 rows(int dir, const int m[4], int) const { return load_rows2_at<NC>(U, g, dir, m); }
+    __device__ __forceinline__ M3<float> full(int dir, const int m[4], int) const { return load_full_at<NC>(U, g, dir, m); }
+    // rows 0, 1 and the row-2 entries of columns 0, 1
+    __device__ __forceinline__ void rows_c01(int dir, const int m[4], int, Rows2& a, float a2r[2], float a2i[2]) const
+    {
+        if constexpr (NC == 12) {
+            a = load_rows2_at<12>(U, g, dir, m);
+            row2_entry(a.re, a.im, 0, a2r[0], a2i[0]);
+            row2_entry(a.re, a.im, 1, a2r[1], a2i[1]);
+        } else {
+            const M3<float> af = load_at(U, g, dir, m);
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                a.re[k] = af.re[k];
+                a.im[k] = af.im[k];
+            }
+            a2r[0] = af.re[6];
+            a2i[0] = af.im[6];
+            a2r[1] = af.re[7];
+            a2i[1] = af.im[7];
+        }
+    }
+};
+
+template <int NC, bool SNAP, class LD>
+__device__ __forceinline__ M3<float> staple_sum_rows(const LD& ld, const Geo& g, int mu, const int n[4], M3<float>* lo)
 {
     M3<float> A;
     m_set_zero(A);
@@ -842,9 +874,9 @@ __device__ __forceinline__ M3<float> staple_sum_rows(const Links<float, NC>& U, 
         npm_mn[nu] = nmn[nu];
         {
             // U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+
-            const Rows2 a = load_rows2_at<NC>(U, g, nu, npm);
-            const M3<float> b = load_full_at<NC>(U, g, mu, npn);
-            const M3<float> c = load_full_at<NC>(U, g, nu, n);
+            const Rows2 a = ld.rows(nu, npm, mu == 0 ? NB_XP : NB_OTHER);
+            const M3<float> b = ld.full(mu, npn, nu == 0 ? NB_XP : NB_OTHER);
+            const M3<float> c = ld.full(nu, n, NB_SAME);
             acc_su3_rows(A, rows_mul_nd(rows_mul_nd(a, b), c));
         }
         {
@@ -852,24 +884,9 @@ __device__ __forceinline__ M3<float> staple_sum_rows(const Links<float, NC>& U, 
             // of the first factor rows 0, 1 and the row-2 entries of columns 0, 1
             Rows2 a;
             float a2r[2], a2i[2];
-            if constexpr (NC == 12) {
-                a = load_rows2_at<12>(U, g, nu, npm_mn);
-                row2_entry(a.re, a.im, 0, a2r[0], a2i[0]);
-                row2_entry(a.re, a.im, 1, a2r[1], a2i[1]);
-            } else {
-                const M3<float> af = load_at(U, g, nu, npm_mn);
-#pragma unroll
-                for (int k = 0; k < 6; k++) {
-                    a.re[k] = af.re[k];
-                    a.im[k] = af.im[k];
-                }
-                a2r[0] = af.re[6];
-                a2i[0] = af.im[6];
-                a2r[1] = af.re[7];
-                a2i[1] = af.im[7];
-            }
-            const M3<float> b = load_full_at<NC>(U, g, mu, nmn);
-            const M3<float> c = load_full_at<NC>(U, g, nu, nmn);
+            ld.rows_c01(nu, npm_mn, NB_OTHER, a, a2r, a2i);
+            const M3<float> b = ld.full(mu, nmn, nu == 0 ? NB_XM : NB_OTHER);
+            const M3<float> c = ld.full(nu, nmn, nu == 0 ? NB_XM : NB_OTHER);
             acc_su3_rows(A, rows_bwd(a, a2r, a2i, b, c));
         }
     }
@@ -893,7 +910,7 @@ __device__ __forceinline__ M3<C> staple_sum(const Links<R, NC>& U, const Geo& g,
                                            M3<C>* lo = nullptr)
 {
     if constexpr (std::is_same<R, float>::value && std::is_same<C, float>::value)
-        return staple_sum_rows<NC, SNAP>(U, g, mu, n, lo);
+        return staple_sum_rows<NC, SNAP>(GlobalLd<NC>{ U, g }, g, mu, n, lo);
     M3<C> A;
     m_set_zero(A);
     // n + mu with mu known only at run time: selects over the unrolled
@@ -990,11 +1007,8 @@ __device__ __forceinline__ int logical_block(int b, int nblocks, int remap)
 // directly, so order N costs N - 1 matrix products.
 //
 // With PS (order 6 only) the same polynomial is evaluated in Paterson-
-// Stockmeyer form, three products instead of five.  In fp32 its rounding
-// leaves a unitarity error of the same sign on every link (a 16^4 HMC
-// trajectory with 18-real links ended 4.3 units of dH away from fp64, the
-// Horner form 6e-4), so it is used only where the result is re-orthonormalized
-// in fp64 before it is stored (12-real links).
+// Stockmeyer form, three products instead of five (see below for the order of
+// its sums, which matters in fp32).
 template <typename R, int N, int L = 2, bool PS = false> __device__ __forceinline__ M3<R> m_exp_ah(const M3<R>& X)
 {
     R nrm = R(0);
@@ -1016,7 +1030,13 @@ template <typename R, int N, int L = 2, bool PS = false> __device__ __forceinlin
     }
     if constexpr (PS && N == 6) {
         // Paterson-Stockmeyer form of the same polynomial, three products:
-        // E = (1 + Y + Y^2/2) + Y^3 (1/6 + Y/24 + Y^2/120 + Y^3/720)
+        // E = 1 + [(Y + Y^2/2) + Y^3 (1/6 + Y/24 + Y^2/120 + Y^3/720)], the
+        // bracket summed at its own scale and the identity added last, as the
+        // Horner form does.  Added first, the small terms of one sign (the
+        // real diagonal of Y^4/24 is positive) were each rounded on the grid
+        // of 1: in fp32 that biased E's unitarity the same way on every link,
+        // and a 16^4 HMC trajectory with 18-real links ended 4.3 units of dH
+        // away from fp64 (added last: 5e-4, as with Horner).
         const M3<R> Y2 = m_mul(Y, Y);
         const M3<R> Y3 = m_mul(Y, Y2);
         M3<R> B, E;
@@ -1028,11 +1048,10 @@ template <typename R, int N, int L = 2, bool PS = false> __device__ __forceinlin
             E.im[q] = Y.im[q] + Y2.im[q] * R(0.5);
         }
 #pragma unroll
-        for (int q = 0; q < 9; q += 4) {
-            B.re[q] += R(1.0 / 6);
-            E.re[q] += R(1);
-        }
+        for (int q = 0; q < 9; q += 4) B.re[q] += R(1.0 / 6);
         mm_acc<false, false>(E, Y3, B);
+#pragma unroll
+        for (int q = 0; q < 9; q += 4) E.re[q] += R(1);
         for (int q = 0; q < s; q++) E = m_mul(E, E);
         return E;
     }

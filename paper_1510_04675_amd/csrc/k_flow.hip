@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double 
             if (!first) x[a] += fa * xo[a];
         }
         store_reals<R, 8>(xslab, cb, x);
-        const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N, 2, NC == 12>(ah_from8(x));
+        const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N, 2, true>(ah_from8(x));
         const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
         M3<R> wn = m_mul(E, w);
         // A 12-real record rebuilds row 2 from rows 0 and 1, so their rounding
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double 
 #pragma unroll
             for (int a = 0; a < 8; a++) y[a] = R(2.25) * x[a] + R(0.25) * xo[a];
             const Links<R, NC> W0{ (uintptr_t)d.aux4, d.cs };
-            M3<R> wt = m_mul(m_exp_ah<R, FlowExpOrder<R>::N, 2, NC == 12>(ah_from8(y)), load_link<R, NC>(W0.slab(mu, par), cb));
+            M3<R> wt = m_mul(m_exp_ah<R, FlowExpOrder<R>::N, 2, true>(ah_from8(y)), load_link<R, NC>(W0.slab(mu, par), cb));
             if constexpr (NC == 12) m_reunit_for_store(wt);
             const Links<R, NC> T{ (uintptr_t)d.aux3, d.cs };
             store_link<R, NC>(T.slab(mu, par), cb, wt);
