@@ -558,12 +558,14 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
             unsigned long long* exh = p.d_exh + (ng > 1 ? p.grp_first[grp] : 0);
             ProfMark pm{ prof_marks, st };
             for (int pass = 0; pass <= o.n_or; pass++) {
-                const int kind = pass == 0 ? 0 : 1;
+                // bits of the phase kernels: 1 overrelaxation, 2 plaquette site
+                // values, 4 fp64 re-orthonormalization of fp32 stores (last pass)
+                const int kind = (pass == 0 ? 0 : 1) | (pass == o.n_or ? 4 : 0);
                 if (pass <= 1 && (rc = pm.begin())) return rc;
                 for (int mu = 0; mu < 4; mu++)
                     for (int par = 0; par < 2; par++) {
-                        const int kk = (fused && pass == o.n_or && par == 1 && mu >= 1) ? 2 : kind;
-                        HIPCHK(launch_phase(p.prec, kk, gph, mu, par, p.d_sweep, k, hb, kind == 0 ? exh : nullptr,
+                        const int kk = kind | ((fused && pass == o.n_or && par == 1 && mu >= 1) ? 2 : 0);
+                        HIPCHK(launch_phase(p.prec, kk, gph, mu, par, p.d_sweep, k, hb, pass == 0 ? exh : nullptr,
                                             st));
                     }
                 if (pass == 0 && (rc = pm.end(0, 8))) return rc;

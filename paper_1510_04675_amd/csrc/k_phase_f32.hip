@@ -8,14 +8,23 @@ namespace msmc {
 hipError_t launch_phase_f32(int prec, int kind, const Grid& gr, int mu, int par, const uint64_t* sweep_base,
                             int sweep_off, HbArgs hb, unsigned long long* exhausted, hipStream_t st)
 {
-    if (prec == PREC_F32) {
-        if (kind == 0) return launch_phase_t<float, 18, 0>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
-        if (kind == 2) return launch_phase_t<float, 18, 2>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
-        return launch_phase_t<float, 18, 1>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
+#define PHASE_F32(NC)                                                                                          \
+    switch (kind) {                                                                                            \
+    case 0: return launch_phase_t<float, NC, 0>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);        \
+    case PH_STORE64:                                                                                           \
+        return launch_phase_t<float, NC, PH_STORE64>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);   \
+    case PH_OR: return launch_phase_t<float, NC, PH_OR>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st); \
+    case PH_OR | PH_STORE64:                                                                                   \
+        return launch_phase_t<float, NC, PH_OR | PH_STORE64>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, \
+                                                              st);                                              \
+    case PH_OR | PH_PLAQ | PH_STORE64:                                                                         \
+        return launch_phase_t<float, NC, PH_OR | PH_PLAQ | PH_STORE64>(gr, mu, par, sweep_base, sweep_off, hb,  \
+                                                                        exhausted, st);                         \
+    default: return hipErrorInvalidValue;                                                                      \
     }
-    if (kind == 0) return launch_phase_t<float, 12, 0>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
-    if (kind == 2) return launch_phase_t<float, 12, 2>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
-    return launch_phase_t<float, 12, 1>(gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
+    if (prec == PREC_F32) PHASE_F32(18)
+    PHASE_F32(12)
+#undef PHASE_F32
 }
 
 }  // namespace msmc

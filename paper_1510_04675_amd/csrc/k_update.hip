@@ -24,7 +24,7 @@ hipError_t launch_phase(int prec, int kind, const Grid& gr, int mu, int par, con
                         int sweep_off, HbArgs hb, unsigned long long* exhausted, hipStream_t st)
 {
     if (gr.nblocks <= 0) return hipSuccess;
-    if (kind < 0 || kind > 2) return hipErrorInvalidValue;
+    if (kind < 0 || kind > 7) return hipErrorInvalidValue;
     if (prec == PREC_F64) return launch_phase_f64(kind, gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);
     if (prec == PREC_F32 || prec == PREC_F32_R12)
         return launch_phase_f32(prec, kind, gr, mu, par, sweep_base, sweep_off, hb, exhausted, st);

@@ -90,12 +90,12 @@ struct HbArgs {
 };
 
 // --- update kernels (k_update.hip) -----------------------------------------
-// One checkerboard phase (mu, parity) of the heat bath (kind 0) or the
-// overrelaxation (kind 1).  Kind 2 is overrelaxation that also writes, for
-// the odd-parity phases mu = 1, 2, 3 of a sweep's last pass, each site's
-// share of the plaquette sum into psite (see k_phase).  Work unit: one link
-// of that direction and parity per thread, bbeg counts ceil(Vh / block)
-// blocks per lattice.
+// One checkerboard phase (mu, parity).  kind is a set of bits (phase.hpp):
+// 1 overrelaxation (else heat bath); 2 also write, for the odd-parity phases
+// mu = 1, 2, 3 of a sweep's last pass, each site's share of the plaquette sum
+// into psite (see k_phase); 4 re-orthonormalize fp32 stores in fp64 (a
+// sweep's last pass).  Work unit: one link of that direction and parity per
+// thread, bbeg counts ceil(Vh / block) blocks per lattice.
 hipError_t launch_phase(int prec, int kind, const Grid& gr, int mu, int par, const uint64_t* sweep_base,
                         int sweep_off, HbArgs hb, unsigned long long* exhausted, hipStream_t st);
 hipError_t launch_phase_f64(int kind, const Grid& gr, int mu, int par, const uint64_t* sweep_base, int sweep_off,

@@ -163,11 +163,17 @@ __device__ __forceinline__ void draw_dir(const Rng& rng, int mu, int sg, int h, 
     g[3] = sr * ct;
 }
 
+// KIND bits: 1 overrelaxation (else heat bath), 2 plaquette site values,
+// 4 fp64 re-orthonormalization of fp32 stores (the last pass of a sweep).
+constexpr int PH_OR = 1, PH_PLAQ = 2, PH_STORE64 = 4;
+
 template <typename R, int NC, int KIND>
 __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const uint64_t* __restrict__ sweep_base,
                                                int sweep_off, HbArgs hb, unsigned long long* exhausted)
 {
     constexpr bool kF64 = std::is_same<R, double>::value;
+    constexpr bool kHB = (KIND & PH_OR) == 0;
+    constexpr bool kPlaq = (KIND & PH_PLAQ) != 0;
     const int lb = logical_block(blockIdx.x, gr.nblocks, gr.remap);
     const int l = find_lattice_p(gr.bbeg, gr.nlat, lb);
     const LatDesc& d = gr.descs[l];
@@ -180,22 +186,22 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
     tiled_coords(g, d.tile, w, par, n);
     const int cb = lex_index(g, n) >> 1;
     Rng rng{ d.seed, d.lid, (uint32_t)lex_index(g, n), 0 };
-    if (KIND == 0) rng.step = *sweep_base + (uint64_t)sweep_off;
+    if (kHB) rng.step = *sweep_base + (uint64_t)sweep_off;
     // fp32 KP: draws of hit 0 ahead of the staple (uniform branch)
-    constexpr bool kPre = !kF64 && KIND == 0 && kPreTrials >= 0;
+    constexpr bool kPre = !kF64 && kHB && kPreTrials >= 0;
     const bool pre = kPre && hb.sampler == 0 && kPreTrials > 0;
     KpPre kp;
     if constexpr (kPre)
         if (pre) kp_precompute(rng, mu, kp);
 
     M3<R> Alo;  // kind 2: the staples of the planes (nu, mu), nu < mu
-    const M3<R> A = staple_sum<R, NC, R, KIND == 2>(U, g, mu, n, &Alo);
+    const M3<R> A = staple_sum<R, NC, R, kPlaq>(U, g, mu, n, &Alo);
     const uintptr_t s = U.slab(mu, par);
     M3<R> u = load_link<R, NC, true>(s, cb);
     M3<R> W = m_mul(u, A);
     const R beta = (R)d.beta;
     const float b23 = (float)(d.beta * (2.0 / 3.0));  // fp32 alpha = (2 beta / 3) k
-    const int nh = (KIND == 0) ? hb.n_hits : 1;
+    const int nh = kHB ? hb.n_hits : 1;
 
     for (int h = 0; h < nh; h++) {
 #pragma unroll
@@ -207,7 +213,7 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
                 if (k == 0.0) continue;
                 const Cx vd[2][2] = { { c_conj(v[0][0]), c_conj(v[1][0]) }, { c_conj(v[0][1]), c_conj(v[1][1]) } };
                 Cx r[2][2];
-                if (KIND == 0) {
+                if (kHB) {
                     const double alpha = 2.0 * beta * k / 3.0;
                     double g0;
                     if (!draw_g0<double>(rng, alpha, mu, sg, h, hb, g0)) {
@@ -228,7 +234,7 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
                 const R k = su2_part(W, i, j, v);
                 if (!(k > R(0))) continue;
                 Q4<R> r;
-                if (KIND == 0) {
+                if (kHB) {
                     const R alpha = b23 * k;
                     R g0;
                     R q[4];
@@ -261,9 +267,20 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
     }
     // fp32 links are re-orthonormalized (rows 0, 1; row 2 their completion)
     // before every store: rounding in a 12-real record would otherwise grow,
-    // because the rebuilt third row feeds back into rows 0 and 1.
-    if constexpr (!kF64) m_reunit(u);
-    if constexpr (KIND == 2) {
+    // because the rebuilt third row feeds back into rows 0 and 1.  In fp32,
+    // rows already within an ulp of unit length are not rescaled at all, and
+    // sub-ulp drifts of one sign (the hardware square roots of the draws) left
+    // |row|^2 - 1 at -1.7e-8 on average (0.2 of an ulp; the plaquette 3e-8
+    // low).  The last pass of a sweep, which stores every link once, does it
+    // in fp64 and rounds once, so the field at the end of every sweep has
+    // unbiased rows (mean 1e-11).
+    if constexpr (!kF64) {
+        if constexpr ((KIND & PH_STORE64) != 0)
+            m_reunit_for_store(u);
+        else
+            m_reunit(u);
+    }
+    if constexpr (kPlaq) {
         // Plaquette sum of the sweep, formed in its last pass: a phase (mu,
         // odd) with mu >= 1 is the last update of every plaquette in the
         // planes (nu, mu), nu < mu, and each of those plaquettes holds
@@ -295,13 +312,17 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
 // allowed (three blocks of 54.5 KB did not fit together on a CU, three of 48
 // KB did).  Blocks of 512 threads are left alone (a cap there would exceed 64
 // KB per block).
+// fp64 records are three times larger: its overrelaxation phases keep at most
+// 4 wavefronts per CU (a 32^4 phase 173.8 -> 166.5 us; its heat bath, again,
+// is faster uncapped at the 8 its registers allow).
 constexpr int kOrWavesPerCu = 12;
+constexpr int kOrWavesPerCuF64 = 4;
 
-static size_t or_lds_bytes(int block)
+static size_t or_lds_bytes(int block, int waves_per_cu)
 {
     const int waves = block / 64;
     if (waves < 1 || waves > 4) return 0;
-    const int blocks_per_cu = kOrWavesPerCu / waves;
+    const int blocks_per_cu = waves_per_cu / waves > 0 ? waves_per_cu / waves : 1;
     return (size_t)(147456 / blocks_per_cu) & ~(size_t)255;
 }
 
@@ -309,7 +330,8 @@ template <typename R, int NC, int KIND>
 static hipError_t launch_phase_t(const Grid& gr, int mu, int par, const uint64_t* sb, int so, HbArgs hb,
                                  unsigned long long* ex, hipStream_t st)
 {
-    const size_t lds = (KIND != 0) ? or_lds_bytes(gr.block) : 0;
+    constexpr int cap = std::is_same<R, double>::value ? kOrWavesPerCuF64 : kOrWavesPerCu;
+    const size_t lds = (KIND & PH_OR) ? or_lds_bytes(gr.block, cap) : 0;
     k_phase<R, NC, KIND><<<gr.nblocks, gr.block, lds, st>>>(gr, mu, par, sb, so, hb, ex);
     return hipGetLastError();
 }
