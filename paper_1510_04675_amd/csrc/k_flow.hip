@@ -89,9 +89,11 @@ __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double 
         const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N, 2, true>(ah_from8(x));
         const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
         M3<R> wn = m_mul(E, w);
-        // A 12-real record rebuilds row 2 from rows 0 and 1, so their rounding
-        // would feed back through every later product: re-orthonormalize first.
-        if constexpr (NC == 12) m_reunit_for_store(wn);
+        // fp32 links are re-orthonormalized (in fp64, rounded once) before
+        // the store: a 12-real record rebuilds row 2 from rows 0 and 1, so
+        // their rounding would feed back through every later product, and an
+        // 18-real one would drift away from SU(3) step by step.
+        if constexpr (std::is_same<R, float>::value) m_reunit_for_store(wn);
         store_link<R, NC>(D.slab(mu, par), cb, wn);
         if (mode == 1) {
             R y[8];
@@ -99,7 +101,7 @@ __global__ void __launch_bounds__(256) k_flow_stage(Grid gr, double eps, double 
             for (int a = 0; a < 8; a++) y[a] = R(2.25) * x[a] + R(0.25) * xo[a];
             const Links<R, NC> W0{ (uintptr_t)d.aux4, d.cs };
             M3<R> wt = m_mul(m_exp_ah<R, FlowExpOrder<R>::N, 2, true>(ah_from8(y)), load_link<R, NC>(W0.slab(mu, par), cb));
-            if constexpr (NC == 12) m_reunit_for_store(wt);
+            if constexpr (std::is_same<R, float>::value) m_reunit_for_store(wt);
             const Links<R, NC> T{ (uintptr_t)d.aux3, d.cs };
             store_link<R, NC>(T.slab(mu, par), cb, wt);
         } else if (mode == 2) {

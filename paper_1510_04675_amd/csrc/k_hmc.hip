@@ -133,9 +133,13 @@ __device__ __forceinline__ void kick_drift_link(const LatDesc& d, int mu, int pa
         const M3<R> E = m_exp_ah<R, ExpOrder<R>::N, 2, true>(i_eps_P(p, (R)eps_drift));
         const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
         M3<R> un = m_mul(E, u);
-        // 12-real records: row 2 is rebuilt from rows 0 and 1, so keep them
-        // orthonormal (their rounding would otherwise feed back).
-        if constexpr (NC == 12) m_reunit_for_store(un);
+        // fp32 links are re-orthonormalized in fp64 and rounded once at every
+        // drift: for 12-real records row 2 is rebuilt from rows 0 and 1, whose
+        // rounding would otherwise feed back; for 18-real records the rounding
+        // of the product leaves a drift away from SU(3) that grows with the
+        // number of steps, and with it an energy error that no longer falls
+        // with the step size (+0.5 in dH after 182 steps at 32^3 x 72).
+        if constexpr (std::is_same<R, float>::value) m_reunit_for_store(un);
         store_link<R, NC>(D.slab(mu, par), cb, un);
     }
 }

@@ -378,6 +378,30 @@ def test_hmc_reduced_precision_dh_at_16_4(m, prec):
     assert abs(p_end - p64_end) < 5e-9, (p_end, p64_end)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp32_r12"])
+def test_hmc_reduced_precision_long_trajectory_at_32_4(m, prec):
+    """A unit trajectory of 200 leapfrog steps (the step counts App. A needs
+    on its finer lattices) at 32^4 from thermalized links, against fp64 from
+    the same links: |dH - dH_fp64| < 0.05 and the stored links within 1e-6 of
+    SU(3).  Every drift rounds the link update; without re-orthonormalizing
+    the stored links those roundings carry the field away from SU(3) (1e-5
+    after 240 steps) and dH off by an amount that grows faster than the step
+    count (+0.5 after 182 steps at 32^3 x 72), which bent the acceptance
+    curve of the finest App. A ensemble."""
+    d = [32] * 4
+    f = field(m, d, prec)
+    m.su3_init_cold(f)
+    m.su3_sweep_hb_or(f, 6.0, 5, 0, 0, 40, m.hb_params(n_or=4, reunit_every=10), record=False)
+    g = field(m, d, "fp64")
+    m.su3_field_copy(g, f)
+    _, dh = m.su3_hmc_trajectory(f, 6.0, 1.0, 200, 5, 0, 11, 0)
+    _, dh64 = m.su3_hmc_trajectory(g, 6.0, 1.0, 200, 5, 0, 11, 0)
+    ok, dev, _ = m.su3_check_field(f, 1e-6)
+    print(f"\n{prec} 32^4, 200 steps: dH {dh:.5f} vs fp64 {dh64:.5f}; largest deviation from SU(3) {dev:.2e}")
+    assert abs(dh - dh64) < 0.05, (dh, dh64)
+    assert ok and dev < 1e-6, dev
+
+
 def test_wilson_flow_matches_oracle(m, orc):
     d = [4, 4, 6, 4]
     U = orc.init_hot(d, 3, 0)
