@@ -157,103 +157,17 @@ __global__ void __launch_bounds__(256) k_kick_drift(Grid gr, double eps_kick, do
     kick_drift_link<R, NC>(d, x.mu, x.par, x.cb, u, A, eps_kick, eps_drift, drift);
 }
 
-// fp32: a block of 512 threads takes the four directions of the same 64
-// checkerboard positions in both parities (wavefront w: parity w >> 2,
-// direction w & 3), i.e. whole x rows when L0 / 2 divides 64.  Each thread
-// puts its own link into LDS; a staple then reads from there the links at its
-// own site and at n +- e_0 (a third of its links at 32^4), which are own links
-// of the block, and the rest from memory.  The walk of the link-walk kernels,
-// two of its blocks at a time, so bbeg counts the same 2 ceil(Vh / 64) blocks.
-constexpr int kPairSlots = 512;
-typedef v2f PairLds[9][kPairSlots];
-
-template <int NC> struct PairLd {
-    GlobalLd<NC> gl;
-    const PairLds& lds;
-    int par, lane, w, w0, Vh, x0h;
-    // slot of the link (dir, m) if it is in the block, else -1
-    __device__ __forceinline__ int slot(int kind, int dir, const int m[4]) const
-    {
-        if (kind == NB_SAME) return par * 256 + dir * 64 + lane;
-        if (kind == NB_OTHER) return -1;
-        const int wn = w - x0h + (m[0] >> 1);  // same row, other parity
-        if (wn < w0 || wn >= w0 + 64 || wn >= Vh) return -1;
-        return (1 - par) * 256 + dir * 64 + (wn - w0);
-    }
-    __device__ __forceinline__ M3<float> from_lds(int sl) const
-    {
-        M3<float> m;
-#pragma unroll
-        for (int k = 0; k < 9; k++) {
-            const v2f v = lds[k][sl];
-            m.re[k] = v.x;
-            m.im[k] = v.y;
-        }
-        return m;
-    }
-    __device__ __forceinline__ M3<float> full(int dir, const int m[4], int kind) const
-    {
-        const int sl = slot(kind, dir, m);
-        return sl >= 0 ? from_lds(sl) : gl.full(dir, m, kind);
-    }
-    __device__ __forceinline__ Rows2 rows(int dir, const int m[4], int kind) const
-    {
-        const int sl = slot(kind, dir, m);
-        if (sl < 0) return gl.rows(dir, m, kind);
-        Rows2 r;
-#pragma unroll
-        for (int k = 0; k < 6; k++) {
-            const v2f v = lds[k][sl];
-            r.re[k] = v.x;
-            r.im[k] = v.y;
-        }
-        return r;
-    }
-    __device__ __forceinline__ void rows_c01(int dir, const int m[4], int kind, Rows2& a, float a2r[2],
-                                             float a2i[2]) const
-    {
-        gl.rows_c01(dir, m, kind, a, a2r, a2i);
-    }
-};
-
+// fp32: the pair walk (PairWalk), 512 threads per block.
 template <int NC>
 __global__ void __launch_bounds__(512, 4) k_kick_drift_pair(Grid gr, double eps_kick, double eps_drift, int drift)
 {
     __shared__ PairLds lds;
-    const int nb2 = gr.nblocks >> 1;
-    const int lb2 = logical_block(blockIdx.x, nb2, gr.remap);
-    int lo = 0, hi = gr.nlat - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (gr.bbeg[mid] <= 2 * lb2)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const LatDesc& d = gr.descs[lo];
-    const Geo g = d.g;
-    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
-    const int par = wv >> 2, mu = wv & 3;
-    const int w0 = (lb2 - (gr.bbeg[lo] >> 1)) * 64;
-    const int w = w0 + lane;
-    const bool valid = w < g.Vh;
-    const Links<float, NC> U{ (uintptr_t)d.U, d.cs };
-    int n[4] = { 0, 0, 0, 0 };
-    int cb = 0;
-    const int own = par * 256 + mu * 64 + lane;
-    if (valid) {
-        tiled_coords(g, d.tile, w, par, n);
-        cb = lex_index(g, n) >> 1;
-        const M3<float> u = load_link<float, NC>(U.slab(mu, par), cb);
-#pragma unroll
-        for (int k = 0; k < 9; k++) lds[k][own] = v2f{ u.re[k], u.im[k] };
-    }
-    __syncthreads();
-    if (!valid) return;
-    const PairLd<NC> ld{ GlobalLd<NC>{ U, g }, lds, par, lane, w, w0, g.Vh, n[0] >> 1 };
-    const M3<float> A = staple_sum_rows<NC, false>(ld, g, mu, n, nullptr);
+    const PairWalk<NC> pw = pair_walk<NC>(gr, lds);
+    if (!pw.valid) return;
+    const PairLd<NC> ld = pw.loader(lds);
+    const M3<float> A = staple_sum_rows<NC, false>(ld, pw.g, pw.mu, pw.n, nullptr);
     // the own link again from LDS rather than held in registers through the staple
-    kick_drift_link<float, NC>(d, mu, par, cb, ld.from_lds(own), A, eps_kick, eps_drift, drift);
+    kick_drift_link<float, NC>(*pw.d, pw.mu, pw.par, pw.cb, ld.from_lds(pw.own), A, eps_kick, eps_drift, drift);
 }
 
 __device__ __forceinline__ double block_sum_256h(double v)
