@@ -429,16 +429,16 @@ def oracle_timing(threads_list=(1, 16)):
         t, _ = timed(lambda: oracle.sweep_hb_or(d16, U, 6.0, 2, 0, 0, 5, n_or=4))
         rec("C2 16^4 cold, 200 sweeps", "5 sweeps", t, t * 40, "x40 sweeps")
         Uc = oracle.init_hot(d8, 7, 0)
-        t1, _ = timed(lambda: oracle.sweep_hb_or(d8, Uc, 5.8, 7, 0, 0, 100, n_or=4))
+        t1, _ = timed(lambda: oracle.sweep_hb_or(d8, Uc, 5.8, 7, 0, 0, 20, n_or=4))
         its = (156, 69, 39)  # steps the paper's tolerance takes on this input
         t2, _ = timed(lambda: oracle.prolongate(d8, Uc, 0.05, 1e-5, 10))
         Uf, _ = oracle.prolongate(d8, Uc, 0.05, 1e-5, 1)
         t3, _ = timed(lambda: oracle.sweep_hb_or(d16, Uf, 6.0, 7, 0, 100, 5, n_or=4))
         t4, _ = timed(lambda: oracle.wilson_flow(d16, Uf, 0.01, 5))
         rec("C3 8^4 x 100 sweeps -> prolongation -> 16^4 x 50 sweeps -> 100 flow steps",
-            "coarse chain whole, 10 steps per prolongation stage, 5 fine sweeps, 5 flow steps",
-            t1 + t2 + t3 + t4, t1 + t2 * sum(its) / 30 + t3 * 10 + t4 * 20,
-            "prolongation x(156+69+39)/30 steps, sweeps x10, flow x20")
+            "20 coarse sweeps, 10 steps per prolongation stage, 5 fine sweeps, 5 flow steps",
+            t1 + t2 + t3 + t4, t1 * 5 + t2 * sum(its) / 30 + t3 * 10 + t4 * 20,
+            "coarse sweeps x5, prolongation x(156+69+39)/30 steps, fine sweeps x10, flow x20")
         tot, tsample = 0.0, 0.0
         for L in (12, 16, 20):
             dl = [L] * 4
@@ -482,6 +482,8 @@ def main():
     ap.add_argument("--only", default="", help="comma list of parts to run (fp64,fp32,fp32_r12,fp32_batch,r12_batch,hmc,multiscale,flow,batch48)")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="time the oracle on bounded samples of each configuration (host only) and exit")
+    ap.add_argument("--no-oracle-configs", action="store_true",
+                    help="skip the oracle's per-configuration timing in the bench line")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-hmc", action="store_true", help="skip the HMC report")
@@ -564,6 +566,14 @@ def main():
         log(f"bench: cpu baseline (oracle, {threads} threads) ...")
         cpu = cpu_baseline(dims, threads)
         log(f"bench: cpu baseline {cpu['value']:.3e} link updates/s")
+    orc_cfg = None
+    if not (a.no_cpu_baseline or a.no_oracle_configs):
+        thr = min(16, os.cpu_count() or 1)
+        log(f"bench: oracle per configuration (bounded samples, 1 and {thr} threads) ...")
+        try:
+            orc_cfg = oracle_timing((1, thr) if thr > 1 else (1,))
+        except Exception as e:  # the bench line is printed regardless
+            orc_cfg = {"error": repr(e)}
     line = {
         "metric": "SU(3) link updates/s (HB+OR, 32^4) FP32-batched vs FP64; % HBM roofline",
         "value": round(head["updates_per_s"], 1),
@@ -598,6 +608,8 @@ def main():
                          "launch": v["launch"]}
                      for k, v in res.items()},
     }
+    if orc_cfg is not None:
+        line["oracle_configs"] = orc_cfg
     if hmc is not None:
         line["hmc"] = hmc
     if ms is not None:
