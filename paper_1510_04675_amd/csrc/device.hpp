@@ -1046,6 +1046,69 @@ __device__ __forceinline__ int logical_block(int b, int nblocks, int remap)
     return (x < r) ? x * (q + 1) + y : r * (q + 1) + (x - r) * q + y;
 }
 
+// For anti-hermitian Y: Y^2 is hermitian and Y Y^2 anti-hermitian, so only
+// their upper triangles are formed (half the multiply-adds of a product) and
+// the lower ones mirrored.  (Y^2)_ij = -sum_k Y_ik conj(Y_jk).
+template <typename R> __device__ __forceinline__ M3<R> m_sq_ah(const M3<R>& Y)
+{
+    M3<R> H;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        R d = R(0);
+#pragma unroll
+        for (int k = 0; k < 3; k++) d -= Y.re[3 * i + k] * Y.re[3 * i + k] + Y.im[3 * i + k] * Y.im[3 * i + k];
+        H.re[4 * i] = d;
+        H.im[4 * i] = R(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = i + 1; j < 3; j++) {
+            R re = R(0), im = R(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                re -= Y.re[3 * i + k] * Y.re[3 * j + k] + Y.im[3 * i + k] * Y.im[3 * j + k];
+                im -= Y.im[3 * i + k] * Y.re[3 * j + k] - Y.re[3 * i + k] * Y.im[3 * j + k];
+            }
+            H.re[3 * i + j] = re;
+            H.im[3 * i + j] = im;
+            H.re[3 * j + i] = re;
+            H.im[3 * j + i] = -im;
+        }
+    return H;
+}
+
+// Y H for anti-hermitian Y and hermitian H (anti-hermitian when they commute,
+// as for H = Y^2): upper triangle formed, lower mirrored, real diagonal zero.
+template <typename R> __device__ __forceinline__ M3<R> m_mul_ah_h(const M3<R>& Y, const M3<R>& H)
+{
+    M3<R> T;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        R d = R(0);
+#pragma unroll
+        for (int k = 0; k < 3; k++) d += Y.re[3 * i + k] * H.im[3 * k + i] + Y.im[3 * i + k] * H.re[3 * k + i];
+        T.re[4 * i] = R(0);
+        T.im[4 * i] = d;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = i + 1; j < 3; j++) {
+            R re = R(0), im = R(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                re += Y.re[3 * i + k] * H.re[3 * k + j] - Y.im[3 * i + k] * H.im[3 * k + j];
+                im += Y.re[3 * i + k] * H.im[3 * k + j] + Y.im[3 * i + k] * H.re[3 * k + j];
+            }
+            T.re[3 * i + j] = re;
+            T.im[3 * i + j] = im;
+            T.re[3 * j + i] = -re;
+            T.im[3 * j + i] = im;
+        }
+    return T;
+}
+
 // Exponential of an anti-hermitian traceless 3x3 matrix X: Taylor series of
 // X / 2^s (Horner, order N) followed by s squarings, with s chosen so that
 // the Frobenius norm of X / 2^s is at most 2^-L (the remainder is then below
@@ -1075,7 +1138,8 @@ template <typename R, int N, int L = 2, bool PS = false> __device__ __forceinlin
         Y.im[k] = X.im[k] * sc;
     }
     if constexpr (PS && N == 6) {
-        // Paterson-Stockmeyer form of the same polynomial, three products:
+        // Paterson-Stockmeyer form of the same polynomial, three products
+        // (the first two on half the entries, Y being anti-hermitian):
         // E = 1 + [(Y + Y^2/2) + Y^3 (1/6 + Y/24 + Y^2/120 + Y^3/720)], the
         // bracket summed at its own scale and the identity added last, as the
         // Horner form does.  Added first, the small terms of one sign (the
@@ -1083,8 +1147,8 @@ template <typename R, int N, int L = 2, bool PS = false> __device__ __forceinlin
         // of 1: in fp32 that biased E's unitarity the same way on every link,
         // and a 16^4 HMC trajectory with 18-real links ended 4.3 units of dH
         // away from fp64 (added last: 5e-4, as with Horner).
-        const M3<R> Y2 = m_mul(Y, Y);
-        const M3<R> Y3 = m_mul(Y, Y2);
+        const M3<R> Y2 = m_sq_ah(Y);
+        const M3<R> Y3 = m_mul_ah_h(Y, Y2);
         M3<R> B, E;
 #pragma unroll
         for (int q = 0; q < 9; q++) {
