@@ -13,6 +13,7 @@
 // the embedded second-order result exp(2 Z1 - Z0) W0 = exp(9/4 X1 + 1/4 X0) W0
 // (X0 = Z0/4, X1 = 8/9 Z1 - 17/9 X0), the third stage its distance to W3.
 #include "kernels.hpp"
+#include "pair_walk.hpp"
 
 namespace msmc {
 

@@ -12,6 +12,7 @@
 // then U_dst = exp(i eps_drift P) U_src; U_src and U_dst are different
 // buffers because the staples of other threads read U_src.
 #include "kernels.hpp"
+#include "pair_walk.hpp"
 
 namespace msmc {
 

@@ -355,6 +355,25 @@ def test_hmc_fp32_dh_tracks_fp64(m, orc):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp32_r12"])
+def test_hmc_reduced_precision_on_partial_rows(m, orc, prec):
+    """The fp32 HMC step takes both parities of 64 positions per block and
+    serves the +-x neighbours from the block's own links when they are there:
+    on 6 x 4 x 8 x 6 an x row holds 3 positions, so blocks start and end in
+    the middle of rows and some +-x neighbours belong to the next block.  One
+    20-step trajectory against the oracle's from the same links."""
+    d = [6, 4, 8, 6]
+    U = orc.init_hot(d, 23, 0)
+    orc.sweep_hb_or(d, U, 6.0, 23, 0, 0, 5)
+    f = field(m, d, prec)
+    m.su3_field_from_host(f, U)
+    Uh = m.su3_field_to_host(f)
+    _, dH = m.su3_hmc_trajectory(f, 6.0, 1.0, 20, 23, 0, 3, 0)
+    _, rdH = orc.hmc_trajectory(d, Uh, 6.0, 1.0, 20, 23, 0, 3, 0)
+    assert abs(dH - rdH) < 0.05 + 0.02 * abs(rdH), (dH, rdH)
+    assert np.max(np.abs(m.su3_field_to_host(f) - Uh)) < 5e-4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_r12"])
 def test_hmc_reduced_precision_dh_at_16_4(m, prec):
     """One 40-step trajectory on a thermalized 16^4 lattice in reduced
     precision against fp64 from the same links (fp64 is pinned to the oracle
