@@ -23,8 +23,6 @@ def _g0_bins(alpha, nbins):
 def test_su2_sampler_distribution(orc, alpha, sampler):
     """g0 has density proportional to sqrt(1-g0^2) exp(alpha g0) on [-1,1]
     (the SU(2) heat-bath law), checked by chi^2 on equal-probability bins."""
-    if sampler == 1 and alpha > 12:
-        pytest.skip("Creutz sampler acceptance is tiny at large alpha")
     n, nb = 200_000, 40
     g, fails = orc.sample_g0(alpha, n, seed=1000 + int(alpha * 10), sampler=sampler, max_tries=4096)
     assert fails == 0
@@ -45,6 +43,21 @@ def test_kp_acceptance_and_exhaustion(orc):
     proposal = integrate.quad(lambda d: np.sqrt(2 * d) * np.exp(-alpha * d), 0, np.inf)[0]
     acc = target / proposal
     assert abs((n - fails) / n - acc) < 5 * np.sqrt(acc * (1 - acc) / n)
+    assert np.all(np.isnan(g) | ((g >= -1) & (g <= 1)))
+
+
+@pytest.mark.parametrize("alpha", [1.0, 4.0, 30.0])
+def test_creutz_acceptance_and_exhaustion(orc, alpha):
+    """Creutz's sampler proposes g0 from exp(alpha g0) on [-1, 1] and accepts
+    with probability sqrt(1 - g0^2): with one trial the exhausted draws occur
+    at 1 - acceptance, acceptance = (integral of sqrt(1-x^2) e^{alpha x}) /
+    (integral of e^{alpha x}) by quadrature (0.76, 0.56 and 0.23 here)."""
+    n = 100_000
+    g, fails = orc.sample_g0(alpha, n, seed=11, sampler=1, max_tries=1)
+    target = integrate.quad(lambda x: np.sqrt(1 - x * x) * np.exp(alpha * (x - 1)), -1, 1, limit=200)[0]
+    proposal = integrate.quad(lambda x: np.exp(alpha * (x - 1)), -1, 1, limit=200)[0]
+    acc = target / proposal
+    assert abs((n - fails) / n - acc) < 5 * np.sqrt(acc * (1 - acc) / n), ((n - fails) / n, acc)
     assert np.all(np.isnan(g) | ((g >= -1) & (g <= 1)))
 
 
