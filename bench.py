@@ -12,8 +12,10 @@ Printed: one JSON line (rank 0) with the headline value (FP32-R12 batched
 link updates/s), the FP64 single-lattice figure, the roofline of the
 dominant kernel (the overrelaxation phase) from HIP events recorded around
 each run of same-kind phase launches, and the FP64 CPU oracle timed on a
-bounded sample.  Extra reports: HMC at 32^4, a multiscale step (16^4 -> 32^4
-prolongation, rethermalization, flow) and the 48-lattice batch.
+bounded sample, together with its timings on bounded samples of every
+workload configuration at 1 and all host threads.  Extra reports: HMC at
+32^4, a multiscale step (16^4 -> 32^4 prolongation, rethermalization,
+flow), the Wilson flow and the 48-lattice batch.
 """
 from __future__ import annotations
 
