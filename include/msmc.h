@@ -70,8 +70,10 @@ typedef struct su3_field_s* su3_field;
  *  n_hb_hits     heat-bath hits per SU(2) subgroup per link (default 1)
  *  hb_max_tries  rejection trials per draw; if all fail the subgroup is left
  *                unchanged (the paper's "attempted updates"), 1..4096
- *  reunit_every  reunitarize after every sweep s with (s+1) % reunit_every
- *                == 0 (0 = never)
+ *  reunit_every  fp64 fields: reunitarize after every sweep s with
+ *                (s+1) % reunit_every == 0 (0 = never).  fp32 and 12-real
+ *                fields leave every sweep re-orthonormalized in fp64 (the
+ *                stores of its last pass), which subsumes it
  *  sampler       SU3_SAMPLER_KP or SU3_SAMPLER_CREUTZ */
 typedef struct {
     int32_t n_or;
@@ -268,7 +270,8 @@ int32_t su3_displaced_loops(su3_field f, double out[5]);
 
 /* Reunitarize every link (Gram-Schmidt of rows 0,1 in fp64).  Not a step of
  * the paper, whose precision is unstated: it returns reduced-precision links
- * to SU(3) (the sweeps do it every reunit_every sweeps). */
+ * to SU(3) (the sweeps do it for fp64 fields every reunit_every sweeps, and
+ * for fp32 fields at the end of every sweep). */
 int32_t su3_reunitarize(su3_field f);
 
 /* Random gauge transformation U_mu(n) -> Om(n) U_mu(n) Om(n+mu)^+ with Om

@@ -549,6 +549,11 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
     // the plaquette is formed in the last overrelaxation pass when the plan
     // has the buffers for it
     const bool fused = o.record && p.d_psite && o.n_or >= 1;
+    // fp32 and 12-real links leave every sweep re-orthonormalized in fp64 by
+    // the stores of its last pass, which leaves nothing for the
+    // reunitarization every reunit_every sweeps to do: it runs on fp64
+    // fields only (and with it the fresh plaquette of such a sweep)
+    const int every = p.prec == PREC_F64 ? o.reunit_every : 0;
     int32_t rc;
     for (int k = 0; k < n_sweeps; k++) {
         // Lattices are independent: each group runs its whole sweep before the
@@ -572,7 +577,7 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
                 if (pass == o.n_or && pass > 0 && (rc = pm.end(1, 8 * o.n_or))) return rc;
             }
         }
-        if (o.reunit_every > 0) HIPCHK(launch_reunit(p.prec, p.grid_link(), p.d_sweep, k, o.reunit_every, st));
+        if (every > 0) HIPCHK(launch_reunit(p.prec, p.grid_link(), p.d_sweep, k, every, st));
         if (o.record) {
             ProfMark pm{ prof_marks, st };
             if ((rc = pm.begin())) return rc;
@@ -580,12 +585,12 @@ static int32_t enqueue_sweeps(const Plan& p, int n_sweeps, const SweepOpts& o, h
                 // site values of the last pass; in a sweep that reunitarizes
                 // the plaquette is taken afresh from the reunitarized links
                 HIPCHK(launch_psite_partial(p.grid_psite(), p.d_partials2, st));
-                if (o.reunit_every > 0)
-                    HIPCHK(launch_plaq_partial_gated(p.prec, p.grid_site(), p.d_partials, p.d_sweep, k,
-                                                     o.reunit_every, st));
+                if (every > 0)
+                    HIPCHK(launch_plaq_partial_gated(p.prec, p.grid_site(), p.d_partials, p.d_sweep, k, every,
+                                                     st));
                 if ((rc = pm.end(2, 1))) return rc;
                 HIPCHK(launch_reduce_pick(p.nlat, p.d_bbeg_site, p.d_partials, p.d_bbeg_psite, p.d_partials2,
-                                          p.d_sweep, k, o.reunit_every, p.d_out, 1, k * p.nlat, st));
+                                          p.d_sweep, k, every, p.d_out, 1, k * p.nlat, st));
             } else {
                 HIPCHK(launch_plaq_partial(p.prec, p.grid_site(), p.d_partials, st));
                 if ((rc = pm.end(2, 1))) return rc;
