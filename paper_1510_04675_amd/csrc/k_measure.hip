@@ -141,11 +141,35 @@ __device__ __forceinline__ float retr_rows01(const float xr[6], const float xi[6
     return t;
 }
 
+// X = A B in fp32 with explicit fused multiply-adds (this unit is compiled
+// without contraction).
+__device__ __forceinline__ M3<float> mul_fma(const M3<float>& a, const M3<float>& b)
+{
+    M3<float> x;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                re = fmaf(a.re[3 * r + k], b.re[3 * k + c], re);
+                re = fmaf(-a.im[3 * r + k], b.im[3 * k + c], re);
+                im = fmaf(a.re[3 * r + k], b.im[3 * k + c], im);
+                im = fmaf(a.im[3 * r + k], b.re[3 * k + c], im);
+            }
+            x.re[3 * r + c] = re;
+            x.im[3 * r + c] = im;
+        }
+    return x;
+}
+
 // sum_{mu<nu} [1 - (1/3) Re Tr U_mu(n) U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+]
-// Each plane term is formed per site and summed in fp64.  18-real fields
-// multiply in fp64; 12-real fields, whose third rows are by construction
-// conj(row0 x row1), form only rows 0 and 1 of the two half-plaquettes in
-// fp32 (the SU(3) identity above).
+// Each plane term is formed per site and summed in fp64.  fp64 fields
+// multiply in fp64; 18-real fp32 fields form the two half-plaquettes in fp32
+// (no SU(3) property assumed) and trace them in fp64; 12-real fields, whose
+// third rows are by construction conj(row0 x row1), form only rows 0 and 1 of
+// the two half-plaquettes in fp32 (the SU(3) identity above).
 template <typename R, int NC, bool GATED = false>
 __global__ void __launch_bounds__(256) k_plaq(Grid gr, double* __restrict__ partials,
                                               const uint64_t* __restrict__ sweep_base = nullptr, int sweep_off = 0,
@@ -181,6 +205,28 @@ __global__ void __launch_bounds__(256) k_plaq(Grid gr, double* __restrict__ part
                     rows01_mul(own[mu], load_at(U, d.g, nu, npm), xr, xi);
                     rows01_mul(own[nu], load_at(U, d.g, mu, npn), yr, yi);
                     acc += 1.0 - (double)retr_rows01(xr, xi, yr, yi) / 3.0;
+                }
+            }
+        } else if constexpr (std::is_same<R, float>::value) {
+            const int cb = lex_index(d.g, s.n) >> 1;
+            const int par = (s.n[0] + s.n[1] + s.n[2] + s.n[3]) & 1;
+            M3<float> own[4];
+#pragma unroll
+            for (int mu = 0; mu < 4; mu++) own[mu] = load_link<float, NC>(U.slab(mu, par), cb);
+#pragma unroll
+            for (int mu = 0; mu < 4; mu++) {
+                int npm[4];
+                shifted(s.n, d.g, mu, 1, 0, 0, npm);
+#pragma unroll
+                for (int nu = mu + 1; nu < 4; nu++) {
+                    int npn[4];
+                    shifted(s.n, d.g, nu, 1, 0, 0, npn);
+                    const M3<float> X = mul_fma(own[mu], load_at(U, d.g, nu, npm));
+                    const M3<float> Y = mul_fma(own[nu], load_at(U, d.g, mu, npn));
+                    double t = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 9; k++) t += (double)fmaf(X.re[k], Y.re[k], X.im[k] * Y.im[k]);
+                    acc += 1.0 - t / 3.0;
                 }
             }
         } else {
