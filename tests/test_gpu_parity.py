@@ -549,6 +549,39 @@ def test_full_size_32_4_fp32_sweep_tracks_oracle(m, orc):
     assert np.count_nonzero(dev > 1e-2) <= dev.size // 10000
 
 
+def test_full_size_benchmark_batch_matches_oracle(m, orc):
+    """The benchmark's workload at full size and in its launch configuration:
+    4 x 32^4 R12 lattices (Haar hot starts, seed 3, lattice ids 0..3) swept
+    as one batch with the autotuner on (lattice groups of at most 224 MiB,
+    one lattice each), 1 HB + 4 OR passes at beta 6.  The first-sweep
+    plaquette of lattices 0 and 3 lies within 1e-6 of the FP64 oracle's sweep
+    of the same stored links (from the rough Haar start the chains separate
+    per link by chaos within the sweep, so only the plaquette bar applies),
+    and lattice 3 equals a separate call bitwise."""
+    d = [32, 32, 32, 32]
+    fs = [field(m, d, "fp32_r12") for _ in range(4)]
+    for i, f in enumerate(fs):
+        m.su3_init_hot(f, 3, i)
+    starts = {i: m.su3_field_to_host(fs[i]) for i in (0, 3)}
+    try:
+        m.su3_autotune(True)
+        pb = m.su3_batch_sweep_hb_or(fs, [6.0] * 4, [3] * 4, [0, 1, 2, 3], 0, 1, P(n_or=4, reunit=10))
+    finally:
+        m.su3_autotune(False)
+    end3 = m.su3_field_to_host(fs[3])
+    for f in fs[:3]:
+        f.close()
+    for i, U in starts.items():
+        href, _ = orc.sweep_hb_or(d, U, 6.0, 3, i, 0, 1, n_or=4, reunit_every=10)
+        print(f"\nlattice {i}: plaquette {pb[0, i]:.10f} oracle {href[0]:.10f}")
+        assert abs(pb[0, i] - href[0]) < 1e-6
+    g = field(m, d, "fp32_r12")
+    m.su3_init_hot(g, 3, 3)
+    h = m.su3_sweep_hb_or(g, 6.0, 3, 3, 0, 1, P(n_or=4, reunit=10))
+    assert h[0] == pb[0, 3]
+    assert np.array_equal(m.su3_field_to_host(g), end3)
+
+
 def test_smallest_extents_match_oracle(m, orc):
     """Extent 2 in every direction (n + mu = n - mu) and mixed 2/4/6 extents:
     FP64 sweeps per link against the oracle."""
