@@ -582,6 +582,35 @@ def test_full_size_benchmark_batch_matches_oracle(m, orc):
     assert np.array_equal(m.su3_field_to_host(g), end3)
 
 
+def test_full_size_32_4_flow_steps_match_oracle(m, orc):
+    """The Wilson flow at the benchmark's 32^4 and launch shapes (FP64: one
+    link per thread; R12: the paired LDS walk): two RK3 steps of eps 0.02
+    from the links of an R12 field roughened by one oracle sweep from a cold
+    start.  FP64 per link within 1e-12 of the oracle's flow of the same
+    links, plaquette 1e-12 and Q 1e-9; R12 plaquette within 2e-8 and Q within
+    1e-4 (the bars of the 16^4 configuration)."""
+    d = [32, 32, 32, 32]
+    U = orc.init_cold(d)
+    orc.sweep_hb_or(d, U, 6.0, 9, 0, 0, 1, n_or=1)
+    fr = field(m, d, "fp32_r12")
+    m.su3_field_from_host(fr, U)
+    Ur = m.su3_field_to_host(fr)
+    f64 = field(m, d, "fp64")
+    m.su3_field_from_host(f64, Ur)
+    m.su3_wilson_flow(f64, 0.02, 2)
+    m.su3_wilson_flow(fr, 0.02, 2)
+    p64, q64 = m.su3_plaquette(f64), m.su3_topological_charge(f64)
+    pr, qr = m.su3_plaquette(fr), m.su3_topological_charge(fr)
+    orc.wilson_flow(d, Ur, 0.02, 2)
+    p_ref, q_ref = orc.plaquette(d, Ur), orc.topological_charge(d, Ur)
+    d64 = float(np.max(np.abs(m.su3_field_to_host(f64) - Ur)))
+    print(f"\n32^4 flow: P fp64 {p64:.12f} r12 {pr:.12f} oracle {p_ref:.12f}; Q fp64 {q64:.9f} r12 {qr:.9f} "
+          f"oracle {q_ref:.9f}; fp64 max link diff {d64:.1e}")
+    assert d64 < 1e-12
+    assert abs(p64 - p_ref) < 1e-12 and abs(q64 - q_ref) < 1e-9
+    assert abs(pr - p_ref) < 2e-8 and abs(qr - q_ref) < 1e-4
+
+
 def test_smallest_extents_match_oracle(m, orc):
     """Extent 2 in every direction (n + mu = n - mu) and mixed 2/4/6 extents:
     FP64 sweeps per link against the oracle."""
