@@ -678,6 +678,26 @@ def test_large_lattice_48_4_fp64_sweep_matches_oracle(m, orc):
     assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
 
 
+@pytest.mark.timeout(600)
+def test_field_beyond_4_gib_64_4_fp64_sweep_matches_oracle(m, orc):
+    """64^4 FP64 (16.8 M sites, a 9.7 GB field whose slabs start beyond 4 GiB,
+    so every 32-bit byte offset would wrap): one sweep of 1 HB + 1 OR per
+    link against the oracle, compared in slices to bound host memory."""
+    d = [64, 64, 64, 64]
+    f = field(m, d)
+    m.su3_init_hot(f, 31, 0)
+    h = m.su3_sweep_hb_or(f, 6.0, 31, 0, 0, 1, P(n_or=1))
+    Ug = m.su3_field_to_host(f)
+    f.close()
+    U = orc.init_hot(d, 31, 0)
+    href, _ = orc.sweep_hb_or(d, U, 6.0, 31, 0, 0, 1, n_or=1)
+    assert abs(h[0] - href[0]) < 1e-13
+    n = Ug.shape[0]
+    step = n // 8
+    dev = max(float(np.max(np.abs(Ug[i:i + step] - U[i:i + step]))) for i in range(0, n, step))
+    assert dev < 1e-12, dev
+
+
 def test_library_owned_field_and_stream(m, orc):
     """A field the library allocates itself (su3_field_create) on a separate
     HIP stream gives bitwise the result of a torch-wrapped field; info reports
