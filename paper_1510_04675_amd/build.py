@@ -2,8 +2,9 @@
 
 Every source under csrc/ is compiled to an object in parallel, then linked
 into paper_1510_04675_amd/lib/libmsmc.so.  Device code is compiled with
-packed fp32 instructions disabled; only *_f32.hip units allow fused
-multiply-add contraction.
+packed fp32 instructions disabled; *_f32.hip units allow fused multiply-add
+contraction and the others are compiled without it, except where a unit
+enables it in its source (the fp64 HMC step and flow stage).
 """
 from __future__ import annotations
 
@@ -19,8 +20,8 @@ OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libmsmc.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["k_phase_f64.hip", "k_phase_f32.hip", "k_update.hip", "k_measure.hip", "k_hmc.hip", "k_flow.hip",
-           "k_prolong.hip", "capi.hip"]
+SOURCES = ["k_phase_f64.hip", "k_phase_f32.hip", "k_update.hip", "k_measure.hip", "k_hmc.hip", "k_hmc_f64.hip",
+           "k_flow.hip", "k_flow_f64.hip", "k_prolong.hip", "capi.hip"]
 ARCH = os.environ.get("MSMC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
