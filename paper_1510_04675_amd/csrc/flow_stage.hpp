@@ -1,7 +1,6 @@
 // flow_stage.hpp -- the per-link stage of the third-order Runge-Kutta
 // Wilson flow (Sec. IV.B), shared by the fp32 kernels (k_flow.hip) and the
-// fp64 kernel (k_flow_f64.hip, a unit of its own because it is compiled with
-// fused multiply-adds).  Notation as in k_flow.hip.
+// fp64 kernel (k_flow_f64.hip).  Notation as in k_flow.hip.
 #pragma once
 
 #include <type_traits>

@@ -1,6 +1,5 @@
 // hmc_step.hpp -- the per-link leapfrog step of the HMC (Sec. IV.E, App. A),
-// shared by the fp32 kernels (k_hmc.hip) and the fp64 kernel (k_hmc_f64.hip,
-// a unit of its own because it is compiled with fused multiply-adds).
+// shared by the fp32 kernels (k_hmc.hip) and the fp64 kernel (k_hmc_f64.hip).
 #pragma once
 
 #include <type_traits>
@@ -69,12 +68,21 @@ __device__ __forceinline__ void kick_drift_link(const LatDesc& d, int mu, int pa
     const uintptr_t pslab = (uintptr_t)d.aux + (uintptr_t)(mu * 2 + par) * d.cs8;
     R p[8];
     load_reals<R, 8>(pslab, cb, p);
-    const R ek = (R)eps_kick;
+    // The kick is formed in fp64 with the step as given and rounded once, and
+    // so is the drift's generator eps P below.  In fp32 the step itself rounds
+    // (1/40 to 1/40 (1 + 1.5e-8)), and a kick that far from the drift's step
+    // unbalances the second-order terms the leapfrog cancels between them
+    // (about 1e4 per step at 32^4): dH then shifted systematically against
+    // fp64 from the same start, -0.010 +- 0.001 per 32^4 trajectory of 40
+    // steps (+0.041 with a fused multiply-add), against -0.002 +- 0.001 now.
 #pragma unroll
-    for (int a = 0; a < 8; a++) p[a] = p[a] - ek * F[a];
+    for (int a = 0; a < 8; a++) p[a] = (R)((double)p[a] - eps_kick * (double)F[a]);
     store_reals<R, 8>(pslab, cb, p);
     if (drift) {
-        const M3<R> E = m_exp_ah<R, ExpOrder<R>::N, 2, true>(i_eps_P(p, (R)eps_drift));
+        double pd[8];
+#pragma unroll
+        for (int a = 0; a < 8; a++) pd[a] = (double)p[a];
+        const M3<R> E = m_exp_ah<R, ExpOrder<R>::N, 2, true>(m_cast<double, R>(i_eps_P(pd, eps_drift)));
         const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
         M3<R> un = m_mul(E, u);
         // fp32 links are re-orthonormalized in fp64 and rounded once at every

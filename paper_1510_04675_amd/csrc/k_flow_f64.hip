@@ -5,8 +5,7 @@
 // headers so that their inline arithmetic is contracted here too: the flow
 // smooths the field rather than amplifying rounding, so contraction (a fifth
 // fewer fp64 instructions, 3.13 -> 2.81 ms per 32^4 step) leaves the links
-// within 1e-15 of the oracle's per step.  The fp32 kernels stay
-// uncontracted, as the fp32 HMC step does.
+// within 1e-15 of the oracle's per step.
 #pragma clang fp contract(fast)
 #include "flow_stage.hpp"
 

@@ -6,9 +6,7 @@
 // operation order because overrelaxation amplifies any rounding difference,
 // a trajectory is not chaotic at its length: contraction cuts a fifth of the
 // fp64 instructions and leaves the links within 1e-15 and dH within 1e-8 of
-// the uncontracted step.  (The fp32 kernels stay uncontracted: there the
-// rounding of the step shifts dH by a small systematic amount, -0.010 per
-// 32^4 trajectory of 40 steps uncontracted against +0.041 contracted.)
+// the uncontracted step.
 #pragma clang fp contract(fast)
 #include "hmc_step.hpp"
 
