@@ -314,9 +314,13 @@ __global__ void __launch_bounds__(512) k_phase(Grid gr, int mu, int par, const u
 // KB per block).
 // fp64 records are three times larger: its overrelaxation phases keep at most
 // 4 wavefronts per CU (a 32^4 phase 173.8 -> 166.5 us; its heat bath, again,
-// is faster uncapped at the 8 its registers allow).
+// is faster uncapped at the 8 its registers allow).  18-real fp32 records,
+// 1.5 times the 12-real ones, keep at most 8 in both kinds of phase (32^4:
+// overrelaxation 72.2 -> 66.1 us, heat bath 78.2 -> 72.1 us; 4 per CU gave
+// 85 us for overrelaxation).
 constexpr int kOrWavesPerCu = 12;
 constexpr int kOrWavesPerCuF64 = 4;
+constexpr int kWavesPerCuF32x18 = 8;
 
 static size_t or_lds_bytes(int block, int waves_per_cu)
 {
@@ -330,8 +334,11 @@ template <typename R, int NC, int KIND>
 static hipError_t launch_phase_t(const Grid& gr, int mu, int par, const uint64_t* sb, int so, HbArgs hb,
                                  unsigned long long* ex, hipStream_t st)
 {
-    constexpr int cap = std::is_same<R, double>::value ? kOrWavesPerCuF64 : kOrWavesPerCu;
-    const size_t lds = (KIND & PH_OR) ? or_lds_bytes(gr.block, cap) : 0;
+    constexpr bool kOr = (KIND & PH_OR) != 0;
+    constexpr int cap = std::is_same<R, double>::value ? (kOr ? kOrWavesPerCuF64 : 0)
+                        : NC == 18                      ? kWavesPerCuF32x18
+                                                        : (kOr ? kOrWavesPerCu : 0);
+    const size_t lds = cap > 0 ? or_lds_bytes(gr.block, cap) : 0;
     k_phase<R, NC, KIND><<<gr.nblocks, gr.block, lds, st>>>(gr, mu, par, sb, so, hb, ex);
     return hipGetLastError();
 }
