@@ -288,8 +288,9 @@ int32_t su3_check_field(su3_field f, double tol, double* max_dev, int64_t* worst
 
 /* Heat-bath draws left unchanged because every trial was rejected (the
  * paper's cap on attempted updates, Sec. IV.A), summed over the last
- * su3_sweep_hb_or or su3_batch_sweep_hb_or call that swept f: after a batch
- * each field holds its own lattice's count. */
+ * su3_sweep_hb_or, su3_sweep_hb_or_noalloc or su3_batch_sweep_hb_or call
+ * that named f: after a batch each field holds its own lattice's count, and
+ * after a call of no sweeps the count is 0. */
 int32_t su3_last_exhausted(su3_field f, int64_t* count);
 
 /* Launch shape of the checkerboard phase kernels: block in {64, 128, 256,

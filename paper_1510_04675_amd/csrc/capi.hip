@@ -1205,7 +1205,10 @@ int32_t su3_batch_sweep_hb_or(const su3_field* fs, int32_t n, const double* beta
         v.push_back(fs[i]);
     }
     hipStream_t st = fs[0]->stream;
-    if (n_sweeps == 0) return SU3_OK;
+    if (n_sweeps == 0) {
+        for (auto* f : v) f->last_exhausted = 0;  // as a single-field call of no sweeps
+        return SU3_OK;
+    }
     if (g_autotune) {
         bool have;
         {

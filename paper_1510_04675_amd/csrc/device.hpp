@@ -1078,47 +1078,23 @@ template <typename R> __device__ __forceinline__ M3<R> m_sq_ah(const M3<R>& Y)
     return H;
 }
 
-// Y H for anti-hermitian Y and hermitian H (anti-hermitian when they commute,
-// as for H = Y^2): upper triangle formed, lower mirrored, real diagonal zero.
-template <typename R> __device__ __forceinline__ M3<R> m_mul_ah_h(const M3<R>& Y, const M3<R>& H)
-{
-    M3<R> T;
-#pragma unroll
-    for (int i = 0; i < 3; i++) {
-        R d = R(0);
-#pragma unroll
-        for (int k = 0; k < 3; k++) d += Y.re[3 * i + k] * H.im[3 * k + i] + Y.im[3 * i + k] * H.re[3 * k + i];
-        T.re[4 * i] = R(0);
-        T.im[4 * i] = d;
-    }
-#pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-        for (int j = i + 1; j < 3; j++) {
-            R re = R(0), im = R(0);
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                re += Y.re[3 * i + k] * H.re[3 * k + j] - Y.im[3 * i + k] * H.im[3 * k + j];
-                im += Y.re[3 * i + k] * H.im[3 * k + j] + Y.im[3 * i + k] * H.re[3 * k + j];
-            }
-            T.re[3 * i + j] = re;
-            T.im[3 * i + j] = im;
-            T.re[3 * j + i] = -re;
-            T.im[3 * j + i] = im;
-        }
-    return T;
-}
-
 // Exponential of an anti-hermitian traceless 3x3 matrix X: Taylor series of
-// X / 2^s (Horner, order N) followed by s squarings, with s chosen so that
-// the Frobenius norm of X / 2^s is at most 2^-L (the remainder is then below
-// 2^(-L (N+1)) / (N+1)!).  The innermost Horner factor 1 + Y/N is formed
-// directly, so order N costs N - 1 matrix products.
+// order N of X / 2^s followed by s squarings, with s chosen so that the
+// Frobenius norm of X / 2^s is at most 2^-L (the remainder is then below
+// 2^(-L (N+1)) / (N+1)!).
 //
-// With PS (order 6 only) the same polynomial is evaluated in Paterson-
-// Stockmeyer form, three products instead of five (see below for the order of
-// its sums, which matters in fp32).
-template <typename R, int N, int L = 2, bool PS = false> __device__ __forceinline__ M3<R> m_exp_ah(const M3<R>& X)
+// The polynomial is evaluated through the Cayley-Hamilton identity of a
+// traceless 3x3 matrix, Y^3 = q Y + d 1 with q = tr(Y^2) / 2 (real for
+// anti-hermitian Y) and d = det Y (imaginary): every power is
+// Y^k = a_k 1 + b_k Y + c_k Y^2 with a_k+1 = c_k d, b_k+1 = a_k + c_k q and
+// c_k+1 = b_k, so E = 1 + (Y + Y^2/2) + (A 1 + B Y + C Y^2) with the complex
+// scalars A, B, C the sums over k = 3..N of (a_k, b_k, c_k) / k!.  One half
+// product (Y^2) and a determinant take the place of N - 1 matrix products
+// (Horner).  The bracket is summed at its own scale, small terms first, and
+// the identity added last: added first, small terms of one sign (the real
+// diagonal of Y^4/24 is positive) are each rounded on the grid of 1, which in
+// fp32 biases E's unitarity the same way on every link.
+template <typename R, int N, int L = 2> __device__ __forceinline__ M3<R> m_exp_ah(const M3<R>& X)
 {
     R nrm = R(0);
 #pragma unroll
@@ -1137,61 +1113,56 @@ template <typename R, int N, int L = 2, bool PS = false> __device__ __forceinlin
         Y.re[k] = X.re[k] * sc;
         Y.im[k] = X.im[k] * sc;
     }
-    if constexpr (PS && N == 6) {
-        // Paterson-Stockmeyer form of the same polynomial, three products
-        // (the first two on half the entries, Y being anti-hermitian):
-        // E = 1 + [(Y + Y^2/2) + Y^3 (1/6 + Y/24 + Y^2/120 + Y^3/720)], the
-        // bracket summed at its own scale and the identity added last, as the
-        // Horner form does.  Added first, the small terms of one sign (the
-        // real diagonal of Y^4/24 is positive) were each rounded on the grid
-        // of 1: in fp32 that biased E's unitarity the same way on every link,
-        // and a 16^4 HMC trajectory with 18-real links ended 4.3 units of dH
-        // away from fp64 (added last: 5e-4, as with Horner).
-        const M3<R> Y2 = m_sq_ah(Y);
-        const M3<R> Y3 = m_mul_ah_h(Y, Y2);
-        M3<R> B, E;
-#pragma unroll
-        for (int q = 0; q < 9; q++) {
-            B.re[q] = Y.re[q] * R(1.0 / 24) + Y2.re[q] * R(1.0 / 120) + Y3.re[q] * R(1.0 / 720);
-            B.im[q] = Y.im[q] * R(1.0 / 24) + Y2.im[q] * R(1.0 / 120) + Y3.im[q] * R(1.0 / 720);
-            E.re[q] = Y.re[q] + Y2.re[q] * R(0.5);
-            E.im[q] = Y.im[q] + Y2.im[q] * R(0.5);
-        }
-#pragma unroll
-        for (int q = 0; q < 9; q += 4) B.re[q] += R(1.0 / 6);
-        mm_acc<false, false>(E, Y3, B);
-#pragma unroll
-        for (int q = 0; q < 9; q += 4) E.re[q] += R(1);
-        for (int q = 0; q < s; q++) E = m_mul(E, E);
-        return E;
-    }
-    // Horner: E = 1 + Y (1 + Y/2 (1 + Y/3 (... (1 + Y/N))))
-    M3<R> E;
+    static_assert(N >= 3, "Cayley-Hamilton form from order 3");
+    const M3<R> Y2 = m_sq_ah(Y);
+    const R q = R(0.5) * (Y2.re[0] + Y2.re[4] + Y2.re[8]);
+    // Im det Y by cofactors along row 0
+    R dl;
     {
-        const R f = R(1) / R(N);
+        const R m0r = Y.re[4] * Y.re[8] - Y.im[4] * Y.im[8] - (Y.re[5] * Y.re[7] - Y.im[5] * Y.im[7]);
+        const R m0i = Y.re[4] * Y.im[8] + Y.im[4] * Y.re[8] - (Y.re[5] * Y.im[7] + Y.im[5] * Y.re[7]);
+        const R m1r = Y.re[3] * Y.re[8] - Y.im[3] * Y.im[8] - (Y.re[5] * Y.re[6] - Y.im[5] * Y.im[6]);
+        const R m1i = Y.re[3] * Y.im[8] + Y.im[3] * Y.re[8] - (Y.re[5] * Y.im[6] + Y.im[5] * Y.re[6]);
+        const R m2r = Y.re[3] * Y.re[7] - Y.im[3] * Y.im[7] - (Y.re[4] * Y.re[6] - Y.im[4] * Y.im[6]);
+        const R m2i = Y.re[3] * Y.im[7] + Y.im[3] * Y.re[7] - (Y.re[4] * Y.im[6] + Y.im[4] * Y.re[6]);
+        dl = (Y.re[0] * m0i + Y.im[0] * m0r) - (Y.re[1] * m1i + Y.im[1] * m1r) + (Y.re[2] * m2i + Y.im[2] * m2r);
+    }
+    // (A, B, C) = sum_k v_k / k! for v_k = (a_k, b_k, c_k) = M^(k-3) v_3,
+    // v_3 = (d, q, 0), M v = (c d, a + c q, b): by Horner in M,
+    // (1/3!) [v_3 + M/4 (v_3 + M/5 (... (v_3 + M/N v_3)))], smallest
+    // terms first and six scalars live.
+    R wAr = R(0), wAi = dl, wBr = q, wBi = R(0), wCr = R(0), wCi = R(0);
 #pragma unroll
-        for (int q = 0; q < 9; q++) {
-            E.re[q] = Y.re[q] * f;
-            E.im[q] = Y.im[q] * f;
+    for (int k = N; k >= 4; k--) {
+        const R f = R(1.0 / k);
+        const R mAr = -wCi * dl, mAi = wCr * dl;
+        const R mBr = wAr + wCr * q, mBi = wAi + wCi * q;
+        const R mCr = wBr, mCi = wBi;
+        wAr = mAr * f;
+        wAi = dl + mAi * f;
+        wBr = q + mBr * f;
+        wBi = mBi * f;
+        wCr = mCr * f;
+        wCi = mCi * f;
+    }
+    const R sixth = R(1.0 / 6);
+    const R Ar = wAr * sixth, Ai = wAi * sixth, Br = wBr * sixth, Bi = wBi * sixth, Cr = wCr * sixth,
+            Ci = wCi * sixth;
+    M3<R> E;
+#pragma unroll
+    for (int e = 0; e < 9; e++) {
+        R sr = Br * Y.re[e] - Bi * Y.im[e] + (Cr * Y2.re[e] - Ci * Y2.im[e]);
+        R si = Br * Y.im[e] + Bi * Y.re[e] + (Cr * Y2.im[e] + Ci * Y2.re[e]);
+        if (e % 4 == 0) {
+            sr += Ar;
+            si += Ai;
         }
-        E.re[0] += R(1);
-        E.re[4] += R(1);
-        E.re[8] += R(1);
+        E.re[e] = (Y.re[e] + Y2.re[e] * R(0.5)) + sr;
+        E.im[e] = (Y.im[e] + Y2.im[e] * R(0.5)) + si;
     }
 #pragma unroll
-    for (int k = N - 1; k >= 1; k--) {
-        M3<R> T = m_mul(Y, E);
-        const R f = R(1) / R(k);
-#pragma unroll
-        for (int q = 0; q < 9; q++) {
-            E.re[q] = T.re[q] * f;
-            E.im[q] = T.im[q] * f;
-        }
-        E.re[0] += R(1);
-        E.re[4] += R(1);
-        E.re[8] += R(1);
-    }
-    for (int q = 0; q < s; q++) E = m_mul(E, E);
+    for (int e = 0; e < 9; e += 4) E.re[e] += R(1);
+    for (int k = 0; k < s; k++) E = m_mul(E, E);
     return E;
 }
 

@@ -74,7 +74,7 @@ __device__ __forceinline__ double flow_stage_link(const LatDesc& d, int mu, int 
         if (!first) x[a] += fa * xo[a];
     }
     store_reals<R, 8>(xslab, cb, x);
-    const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N, 2, true>(ah_from8(x));
+    const M3<R> E = m_exp_ah<R, FlowExpOrder<R>::N, 2>(ah_from8(x));
     const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
     M3<R> wn = m_mul(E, w);
     // fp32 links are re-orthonormalized (in fp64, rounded once) before the
@@ -89,7 +89,7 @@ __device__ __forceinline__ double flow_stage_link(const LatDesc& d, int mu, int 
 #pragma unroll
         for (int a = 0; a < 8; a++) y[a] = R(2.25) * x[a] + R(0.25) * xo[a];
         const Links<R, NC> W0{ (uintptr_t)d.aux4, d.cs };
-        M3<R> wt = m_mul(m_exp_ah<R, FlowExpOrder<R>::N, 2, true>(ah_from8(y)), load_link<R, NC>(W0.slab(mu, par), cb));
+        M3<R> wt = m_mul(m_exp_ah<R, FlowExpOrder<R>::N, 2>(ah_from8(y)), load_link<R, NC>(W0.slab(mu, par), cb));
         if constexpr (std::is_same<R, float>::value) m_reunit_for_store(wt);
         const Links<R, NC> T{ (uintptr_t)d.aux3, d.cs };
         store_link<R, NC>(T.slab(mu, par), cb, wt);

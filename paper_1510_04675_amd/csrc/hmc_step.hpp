@@ -82,7 +82,7 @@ __device__ __forceinline__ void kick_drift_link(const LatDesc& d, int mu, int pa
         double pd[8];
 #pragma unroll
         for (int a = 0; a < 8; a++) pd[a] = (double)p[a];
-        const M3<R> E = m_exp_ah<R, ExpOrder<R>::N, 2, true>(m_cast<double, R>(i_eps_P(pd, eps_drift)));
+        const M3<R> E = m_exp_ah<R, ExpOrder<R>::N, 2>(m_cast<double, R>(i_eps_P(pd, eps_drift)));
         const Links<R, NC> D{ (uintptr_t)d.aux2, d.cs };
         M3<R> un = m_mul(E, u);
         // fp32 links are re-orthonormalized in fp64 and rounded once at every

@@ -177,7 +177,8 @@ def test_batch_exhaustion_counts_per_lattice(m, orc, gbytes):
     """With one heat-bath trial per draw at beta = 1 many draws are left
     unchanged; after a batched call each field reports its own lattice's
     count (equal to the oracle's for that lattice alone), whether the batch
-    runs as one lattice group or one group per lattice."""
+    runs as one lattice group or one group per lattice, and 0 after a call
+    of no sweeps."""
     shapes = [[4, 4, 4, 4], [4, 2, 4, 2], [6, 4, 2, 4]]
     betas = [1.0, 0.8, 1.2]
     m.su3_set_group_bytes(gbytes)
@@ -195,6 +196,10 @@ def test_batch_exhaustion_counts_per_lattice(m, orc, gbytes):
         assert ex > 0
         assert counts[i] == ex, (i, counts, ex)
         assert np.max(np.abs(m.su3_field_to_host(fs[i]) - U)) < 1e-12
+    # a call of no sweeps reports no exhausted draws, batched or not
+    m.su3_batch_sweep_hb_or(fs[:2], betas[:2], [30, 31], [0, 1], 7, 0, P(n_or=1, tries=1))
+    m.su3_sweep_hb_or(fs[2], betas[2], 32, 2, 7, 0, P(n_or=1, tries=1))
+    assert [m.su3_last_exhausted(f) for f in fs] == [0, 0, 0]
 
 
 def fp32_link_stats(Ugpu, Uref):
