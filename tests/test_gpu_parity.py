@@ -347,6 +347,24 @@ def test_hmc_trajectory_matches_oracle(m, orc):
     assert np.array_equal(m.su3_field_to_host(f), before)
 
 
+def test_hmc_coarse_steps_match_oracle(m, orc):
+    """FP64 HMC with steps of 1/2: the drift's generators have norms near 1,
+    beyond the 1/4 up to which the link exponential takes its polynomial
+    directly, so it scales and squares.  Links and dH against the oracle's
+    series summed to convergence (no Metropolis step, so the evolved field
+    is kept)."""
+    d = [4, 4, 4, 4]
+    U = orc.init_hot(d, 8, 0)
+    orc.sweep_hb_or(d, U, 6.0, 8, 0, 0, 4)
+    f = field(m, d)
+    m.su3_field_from_host(f, U)
+    _, dH = m.su3_hmc_trajectory(f, 6.0, 1.0, 2, 8, 0, 4, 0)
+    _, rdH = orc.hmc_trajectory(d, U, 6.0, 1.0, 2, 8, 0, 4, 0)
+    assert abs(dH) > 1.0  # a coarse step: far from energy conservation
+    assert abs(dH - rdH) < 1e-8 * max(1.0, abs(rdH)), (dH, rdH)
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-11
+
+
 def test_hmc_fp32_dh_tracks_fp64(m, orc):
     d = [8, 8, 4, 4]
     U = orc.init_hot(d, 6, 0)
@@ -434,6 +452,20 @@ def test_wilson_flow_matches_oracle(m, orc):
     m.su3_field_from_host(f, U)
     m.su3_wilson_flow(f, 0.02, 5)
     orc.wilson_flow(d, U, 0.02, 5)
+    assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
+    assert abs(m.su3_topological_charge(f) - orc.topological_charge(d, U)) < 1e-11
+
+
+def test_coarse_flow_steps_match_oracle(m, orc):
+    """FP64 flow steps of 0.5 from a hot start: stage generators beyond norm
+    1/4, so the link exponential scales and squares; links and Q against the
+    oracle."""
+    d = [4, 4, 4, 6]
+    U = orc.init_hot(d, 13, 0)
+    f = field(m, d)
+    m.su3_field_from_host(f, U)
+    m.su3_wilson_flow(f, 0.5, 2)
+    orc.wilson_flow(d, U, 0.5, 2)
     assert np.max(np.abs(m.su3_field_to_host(f) - U)) < 1e-12
     assert abs(m.su3_topological_charge(f) - orc.topological_charge(d, U)) < 1e-11
 
