@@ -147,7 +147,11 @@ int32_t su3_prolongate(su3_field coarse, su3_field fine, double c, double rel_to
  * {n_or 4, n_hb_hits 1, hb_max_tries 64, reunit_every 10, KP}; on fp64
  * fields, whose links stay in SU(3) to rounding, pass reunit_every = 0 to
  * follow the paper's schedule exactly.  The count of exhausted draws is
- * kept per field (su3_last_exhausted). */
+ * kept per field (su3_last_exhausted).  At beta = 0 the draw's weight
+ * exp(alpha g0) has alpha = 0, where neither sampler proposes an acceptable
+ * g0: every heat-bath draw is exhausted and leaves its link unchanged (the
+ * beta = 0 ensemble is the Haar measure of su3_init_hot); overrelaxation does
+ * not depend on beta. */
 int32_t su3_sweep_hb_or(su3_field f, double beta, uint32_t seed, uint32_t lattice_id, uint64_t first_sweep,
                         int32_t n_sweeps, const su3_hb_params* p, double* plaq_hist);
 

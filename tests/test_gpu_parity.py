@@ -202,6 +202,27 @@ def test_batch_exhaustion_counts_per_lattice(m, orc, gbytes):
     assert [m.su3_last_exhausted(f) for f in fs] == [0, 0, 0]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_r12"])
+def test_beta_zero_heat_bath_matches_oracle(m, orc, prec):
+    """beta = 0, heat bath only: every draw exhausted on both sides (3 per
+    link and hit), the fp64 links unchanged bit for bit and the 12-real
+    plaquette unchanged to its rounding."""
+    d = [4, 2, 4, 6]
+    U = orc.init_hot(d, 6, 0)
+    f = field(m, d, prec)
+    m.su3_field_from_host(f, U)
+    before = m.su3_field_to_host(f)
+    p0 = m.su3_plaquette(f)
+    m.su3_sweep_hb_or(f, 0.0, 6, 0, 0, 2, P(n_or=0, tries=3), record=False)
+    _, ex = orc.sweep_hb_or(d, U, 0.0, 6, 0, 0, 2, n_or=0, hb_max_tries=3)
+    assert ex == 2 * 3 * 4 * int(np.prod(d))
+    assert m.su3_last_exhausted(f) == ex
+    if prec == "fp64":
+        assert np.array_equal(m.su3_field_to_host(f), before)
+    else:
+        assert abs(m.su3_plaquette(f) - p0) < 1e-6
+
+
 def fp32_link_stats(Ugpu, Uref):
     """Per-link largest component deviation: median, 99.9th percentile, max."""
     dev = np.max(np.abs(Ugpu - Uref), axis=(2, 3, 4)).ravel()

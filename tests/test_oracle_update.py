@@ -78,6 +78,25 @@ def test_or_conserves_action_and_is_reversible(orc):
     assert np.max(np.abs(U - U0)) < 1e-12
 
 
+@pytest.mark.parametrize("sampler", [0, 1])
+def test_beta_zero_heat_bath_is_exhausted(orc, sampler):
+    """At beta = 0 the draw's weight exp(alpha g0) has alpha = 0 (Sec. IV.A):
+    the Kennedy-Pendleton proposal delta = e / alpha is infinite and the
+    Creutz inversion 0 / 0, so no trial is accepted.  Every subgroup draw of
+    every hit is then counted exhausted and the links are left as they were;
+    overrelaxation, which does not involve beta, still moves them."""
+    d = [4, 2, 4, 2]
+    U = orc.init_hot(d, 4, 0)
+    U0 = U.copy()
+    n_links = 4 * int(np.prod(d))
+    _, ex = orc.sweep_hb_or(d, U, 0.0, 4, 0, 0, 2, n_or=0, n_hb_hits=2, hb_max_tries=3, sampler=sampler)
+    assert ex == 2 * 2 * 3 * n_links
+    assert np.array_equal(U, U0)
+    _, ex = orc.sweep_hb_or(d, U, 0.0, 4, 0, 2, 1, n_or=1, hb_max_tries=3, sampler=sampler)
+    assert ex == 3 * n_links
+    assert np.max(np.abs(U - U0)) > 1e-2
+
+
 def test_hb_lowers_action_from_hot_start(orc):
     d = [4, 4, 4, 4]
     U = orc.init_hot(d, 1, 0)
