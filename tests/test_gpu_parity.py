@@ -477,6 +477,21 @@ def test_wilson_flow_matches_oracle(m, orc):
     assert abs(m.su3_topological_charge(f) - orc.topological_charge(d, U)) < 1e-11
 
 
+def test_zero_length_trajectory_and_flow_are_identities(m, orc):
+    """FP64 HMC with tau = 0 and flow steps of 0: the exponential of a zero
+    generator is the identity and every kick zero, so the links come back bit
+    for bit and dH is 0 exactly, as in the oracle."""
+    d = [4, 2, 4, 6]
+    U = orc.init_hot(d, 10, 0)
+    f = field(m, d)
+    m.su3_field_from_host(f, U)
+    acc, dH = m.su3_hmc_trajectory(f, 6.0, 0.0, 5, 10, 0, 0, 1)
+    assert acc and dH == 0.0
+    assert np.array_equal(m.su3_field_to_host(f), U)
+    m.su3_wilson_flow(f, 0.0, 3)
+    assert np.array_equal(m.su3_field_to_host(f), U)
+
+
 def test_coarse_flow_steps_match_oracle(m, orc):
     """FP64 flow steps of 0.5 from a hot start: stage generators beyond norm
     1/4, so the link exponential scales and squares; links and Q against the

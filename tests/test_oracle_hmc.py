@@ -88,6 +88,20 @@ def test_leapfrog_is_reversible_and_keeps_su3(orc):
     assert np.max(np.abs(p + p0)) < 1e-10
 
 
+def test_zero_length_trajectory_and_flow_are_identities(orc):
+    """tau = 0 and flow steps of 0: exp(0) is the identity and every kick is
+    zero, so the links come back unchanged bit for bit and dH is 0 exactly
+    (the same sums over the same values)."""
+    d = [4, 2, 2, 4]
+    U = orc.init_hot(d, 9, 0)
+    U0 = U.copy()
+    acc, dH = orc.hmc_trajectory(d, U, 6.0, 0.0, 5, 9, 0, 0, 1)
+    assert acc and dH == 0.0
+    assert np.array_equal(U, U0)
+    orc.wilson_flow(d, U, 0.0, 3)
+    assert np.array_equal(U, U0)
+
+
 def test_momenta_are_standard_normal(orc):
     p = orc.hmc_momenta([8, 8, 8, 8], 3, 1, 5)
     x = p.ravel()
