@@ -45,11 +45,12 @@ __global__ void __launch_bounds__(512, 4) k_flow_stage_pair(Grid gr, double eps,
                                                             int mode, double* __restrict__ partials)
 {
     __shared__ PairLds lds;
+    __shared__ PairQLds qlds;
     const PairWalk<NC> pw = pair_walk<NC>(gr, lds);
+    const PairLd<NC> ld = pw.loader(lds);
+    const M3<float> A = pair_staple<NC>(pw, ld, qlds);
     double dist = 0.0;
     if (pw.valid) {
-        const PairLd<NC> ld = pw.loader(lds);
-        const M3<float> A = staple_sum_rows<NC, false>(ld, pw.g, pw.mu, pw.n, nullptr);
         dist = flow_stage_link<float, NC>(*pw.d, pw.mu, pw.par, pw.cb, ld.from_lds(pw.own), A, eps, cz, ca, first,
                                           mode);
     }

@@ -79,10 +79,11 @@ template <int NC>
 __global__ void __launch_bounds__(512, 4) k_kick_drift_pair(Grid gr, double eps_kick, double eps_drift, int drift)
 {
     __shared__ PairLds lds;
+    __shared__ PairQLds qlds;
     const PairWalk<NC> pw = pair_walk<NC>(gr, lds);
-    if (!pw.valid) return;
     const PairLd<NC> ld = pw.loader(lds);
-    const M3<float> A = staple_sum_rows<NC, false>(ld, pw.g, pw.mu, pw.n, nullptr);
+    const M3<float> A = pair_staple<NC>(pw, ld, qlds);
+    if (!pw.valid) return;
     // the own link again from LDS rather than held in registers through the staple
     kick_drift_link<float, NC>(*pw.d, pw.mu, pw.par, pw.cb, ld.from_lds(pw.own), A, eps_kick, eps_drift, drift);
 }
