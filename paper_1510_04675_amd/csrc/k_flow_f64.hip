@@ -8,10 +8,12 @@
 // within 1e-15 of the oracle's per step.
 #pragma clang fp contract(fast)
 #include "flow_stage.hpp"
+#include "pair_walk.hpp"
 
 namespace msmc {
 
-// One link per thread in the link walk of four directions of 64 sites;
+// One link per thread in the link walk of four directions of 64 sites, the
+// forward staple products shared within a site (walk_staple_f64);
 // mode 2 stores the block maxima of the distance into partials[logical
 // block] (0 for the padding threads).  Held at 3 wavefronts per SIMD (168
 // VGPRs): at 170 the compiler would leave it 2.
@@ -19,12 +21,13 @@ template <typename R, int NC>
 __global__ void __launch_bounds__(256, 3) k_flow_stage(Grid gr, double eps, double cz, double ca, int first, int mode,
                                                     double* __restrict__ partials)
 {
+    __shared__ WalkQLds qlds;
     const LinkWalk lw = link_walk(gr);
+    const LatDesc& d = gr.descs[lw.l];
+    const Links<R, NC> W{ (uintptr_t)d.U, d.cs };
+    const M3<R> A = walk_staple_f64<NC>(lw, W, d.g, qlds);
     double dist = 0.0;
     if (lw.valid) {
-        const LatDesc& d = gr.descs[lw.l];
-        const Links<R, NC> W{ (uintptr_t)d.U, d.cs };
-        const M3<R> A = staple_sum<R, NC, R>(W, d.g, lw.mu, lw.n);
         const M3<R> w = load_link<R, NC>(W.slab(lw.mu, lw.par), lw.cb);
         dist = flow_stage_link<R, NC>(d, lw.mu, lw.par, lw.cb, w, A, eps, cz, ca, first, mode);
     }

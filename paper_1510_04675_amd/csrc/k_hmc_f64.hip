@@ -9,19 +9,22 @@
 // the uncontracted step.
 #pragma clang fp contract(fast)
 #include "hmc_step.hpp"
+#include "pair_walk.hpp"
 
 namespace msmc {
 
-// One link per thread in the link walk of four directions of 64 sites, held
-// at 3 wavefronts per SIMD (168 VGPRs).
+// One link per thread in the link walk of four directions of 64 sites, the
+// forward staple products shared within a site (walk_staple_f64), held at 3
+// wavefronts per SIMD (168 VGPRs).
 template <typename R, int NC>
 __global__ void __launch_bounds__(256, 3) k_kick_drift(Grid gr, double eps_kick, double eps_drift, int drift)
 {
+    __shared__ WalkQLds qlds;
     const LinkWalk x = link_walk(gr);
-    if (!x.valid) return;
     const LatDesc& d = gr.descs[x.l];
     const Links<R, NC> U{ (uintptr_t)d.U, d.cs };
-    const M3<R> A = staple_sum<R, NC, R>(U, d.g, x.mu, x.n);
+    const M3<R> A = walk_staple_f64<NC>(x, U, d.g, qlds);
+    if (!x.valid) return;
     const M3<R> u = load_link<R, NC>(U.slab(x.mu, x.par), x.cb);
     kick_drift_link<R, NC>(d, x.mu, x.par, x.cb, u, A, eps_kick, eps_drift, drift);
 }

@@ -1,6 +1,7 @@
 // pair_walk.hpp -- the thread -> link walk of the fp32 kernels that update
 // all 4V links at once and read neighbour links (HMC step, flow stage), with
-// the block's own links in LDS.
+// the block's own links in LDS; and the staple sums of these kernels, fp32
+// and fp64, with the forward products shared within a site.
 #pragma once
 
 #include "kernels.hpp"
@@ -215,6 +216,83 @@ __device__ __forceinline__ M3<float> pair_staple(const PairWalk<NC>& pw, const P
             const M3<float> c = ld.full(nu, nmn, nu == 0 ? NB_XM : NB_OTHER);
             acc_su3_rows(A, rows_bwd(a, a2r, a2i, b, c));
         }
+    }
+    return A;
+}
+
+// The fp64 kernels' link walk (one parity, the four directions of 64 sites
+// per block of 256) shares the forward products the same way.  Q is passed
+// whole (its adjoint is then exactly that of the computed Q, so no property
+// of the links is assumed) and in two rounds of three planes, (0,1), (0,2),
+// (0,3) and then (1,2), (1,3), (2,3), formed by directions 1, 2, 3 and then
+// 0, 3, 2, so that three blocks still share a CU (27.6 KB of LDS each).
+// Every thread of the block must call it (it holds barriers); the result is
+// meaningful only where lw.valid.
+typedef v2d WalkQLds[3][9][64];
+
+template <int NC>
+__device__ __forceinline__ M3<double> walk_staple_f64(const LinkWalk& lw, const Links<double, NC>& U, const Geo& g,
+                                                      WalkQLds& qlds)
+{
+    constexpr int pa[kPairPlanes] = { 0, 0, 0, 1, 1, 2 }, pb[kPairPlanes] = { 1, 2, 3, 2, 3, 3 };
+    constexpr int owner[kPairPlanes] = { 1, 2, 3, 0, 3, 2 };
+    const int mu = lw.mu, lane = (int)threadIdx.x & 63;
+    M3<double> A;
+    m_set_zero(A);
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        if (r) __syncthreads();  // the first round's Q are read before they are overwritten
+        if (lw.valid) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const int p = 3 * r + k;
+                if (owner[p] != mu) continue;
+                const int a = pa[p], b = pb[p];
+                int na[4] = { lw.n[0], lw.n[1], lw.n[2], lw.n[3] };
+                na[a] = wrap_add(lw.n[a], 1, g.L[a]);
+                int nb[4] = { lw.n[0], lw.n[1], lw.n[2], lw.n[3] };
+                nb[b] = wrap_add(lw.n[b], 1, g.L[b]);
+                const M3<double> q = m_mul_nd(load_at(U, g, b, na), load_at(U, g, a, nb));
+#pragma unroll
+                for (int e = 0; e < 9; e++) qlds[k][e][lane] = v2d{ q.re[e], q.im[e] };
+            }
+        }
+        __syncthreads();
+        if (lw.valid) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const int p = 3 * r + k, a = pa[p], b = pb[p];
+                if (mu != a && mu != b) continue;
+                M3<double> q;
+#pragma unroll
+                for (int e = 0; e < 9; e++) {
+                    const v2d v = qlds[k][e][lane];
+                    q.re[e] = v.x;
+                    q.im[e] = v.y;
+                }
+                const int nu = mu == a ? b : a;
+                const M3<double> un = load_at(U, g, nu, lw.n);
+                // U_nu(n+mu) U_mu(n+nu)^+ U_nu(n)^+: Q U_nu(n)^+ for mu < nu, else Q^+ U_nu(n)^+
+                if (mu == a)
+                    mm_acc<false, true>(A, q, un);
+                else
+                    mm_acc<true, true>(A, q, un);
+            }
+        }
+    }
+    if (!lw.valid) return A;
+    int npm[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) npm[k] = (k == mu) ? wrap_add(lw.n[k], 1, g.L[k]) : lw.n[k];
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        // U_nu(n+mu-nu)^+ U_mu(n-nu)^+ U_nu(n-nu)
+        int nmn[4] = { lw.n[0], lw.n[1], lw.n[2], lw.n[3] };
+        nmn[nu] = wrap_add(lw.n[nu], -1, g.L[nu]);
+        int npm_mn[4] = { npm[0], npm[1], npm[2], npm[3] };
+        npm_mn[nu] = nmn[nu];
+        mm_acc<false, false>(A, m_mul_dd(load_at(U, g, nu, npm_mn), load_at(U, g, mu, nmn)), load_at(U, g, nu, nmn));
     }
     return A;
 }
